@@ -1,0 +1,335 @@
+/*
+ * prx.h -- C ABI of the Pauli-rotation state-vector engine for AMD MI355X
+ * (gfx950).
+ *
+ * The library applies long sequences of Pauli rotations exp(i phi P) to a
+ * full 2^n complex state held in device memory and returns overlaps
+ * <psi0|psi>.  The rotation sequences come from first- and second-order
+ * Trotter, qDRIFT and the partially randomised product formula.
+ *
+ * Conventions (paper, "Software implementation" and Supplementary Methods,
+ * "Pauli-string bit representation"):
+ *   - Qubit q is bit q of an amplitude index; qubit 0 is the least
+ *     significant bit and carries the first tensor factor.
+ *   - A Pauli string is a pair of masks (x, z): bit q of x is set iff the
+ *     letter on qubit q is X or Y, bit q of z iff it is Y or Z.
+ *   - P|j> = i^{popcount(x & z)} (-1)^{popcount(j & z)} |j XOR x>: the
+ *     phase counts the Y letters (mod 4) and the sign is taken from the
+ *     source index j.
+ *   - exp(i phi P) = cos(phi) I + i sin(phi) P.
+ *   - A schedule lists rotations in application order: entry 0 acts first.
+ *   - Time evolution is exp(+i t H).
+ *
+ * Memory and ownership:
+ *   - States are caller-owned device buffers of 2^n contiguous complex
+ *     numbers: interleaved (re, im) float pairs for PRX_C64, double pairs
+ *     for PRX_C128.  Amplitude k is basis state |k>.  Base address aligned
+ *     to 16 bytes.
+ *   - Workspaces are caller-owned device buffers (aligned to 256 bytes)
+ *     whose size the library reports.  The library itself never allocates
+ *     device memory.
+ *   - Streams are hipStream_t values passed as void*; NULL is the default
+ *     stream.  Work is enqueued on that stream only.
+ *   - Handles (prx_ham, prx_sched, prx_plan) are library-owned host objects,
+ *     immutable after creation except where stated, and may be shared by
+ *     threads for reading.
+ *
+ * Errors: every call returns a prx_status; nothing throws or aborts across
+ * the ABI.  On failure prx_last_error() describes the cause (thread-local,
+ * valid until the next failing call on the same thread).  Outputs are left
+ * untouched on failure unless stated.
+ */
+#ifndef PRX_H
+#define PRX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PRX_OK = 0,
+    PRX_ERR_INVALID = 1,     /* bad argument: range, null pointer, non-finite value, size */
+    PRX_ERR_OOM = 2,         /* host allocation failed */
+    PRX_ERR_HIP = 3,         /* a HIP runtime call failed; prx_last_error() has its string */
+    PRX_ERR_UNSUPPORTED = 4  /* valid request the library cannot serve (size, dtype, option) */
+} prx_status;
+
+typedef enum { PRX_C64 = 1, PRX_C128 = 2 } prx_dtype;
+
+/* Kernel family used by prx_plan_create / prx_apply_range.
+ *   PLAIN: one HBM sweep per rotation (pair update, or diagonal when x = 0).
+ *   FUSED: several rotations per HBM sweep (span and tile kernels chosen by
+ *          the planner), applying exactly the same rotation product.
+ *   AUTO:  FUSED with tile size, chunk rank and fusion depth taken from the
+ *          autotune cache when it has an entry for (n, dtype). */
+typedef enum { PRX_PLAIN = 0, PRX_FUSED = 1, PRX_AUTO = 2 } prx_kernel;
+
+/* Term ordering used when a schedule is built.
+ *   NONE:      terms in the order given.
+ *   COMMUTING: as NONE; the planner may additionally swap adjacent
+ *              commuting rotations, which leaves the product unchanged.
+ *   SUFFIX:    the deterministic terms are stably sorted by (x, z) taken as
+ *              unsigned integers (lexicographic ordering, Methods "Data
+ *              analysis"), which defines a different product formula; the
+ *              sorted list is what prx_sched_view returns. */
+typedef enum {
+    PRX_REORDER_NONE = 0,
+    PRX_REORDER_COMMUTING = 1,
+    PRX_REORDER_SUFFIX = 2
+} prx_reorder;
+
+typedef struct prx_ham prx_ham;
+typedef struct prx_sched prx_sched;
+typedef struct prx_plan prx_plan;
+
+/* ------------------------------------------------------------------ */
+/* Hamiltonian H = sum_l h_l P_l, lambda = sum_l |h_l|                 */
+/* (Methods, "Hamiltonian simulation").                                */
+/* ------------------------------------------------------------------ */
+
+/* Copies L terms (host arrays x[L], z[L], h[L]).  INVALID if n not in
+ * [1, 63], L = 0, a mask has a bit >= n, or an h is not finite. */
+prx_status prx_ham_create(int n, size_t L, const uint64_t *x, const uint64_t *z,
+                          const double *h, prx_ham **out);
+void prx_ham_destroy(prx_ham *ham);
+/* lambda = sum |h_l| accumulated left to right in FP64. */
+prx_status prx_ham_lambda(const prx_ham *ham, double *out);
+
+/* ------------------------------------------------------------------ */
+/* Schedules: rotation lists (x_j, z_j, phi_j) in application order.   */
+/* ------------------------------------------------------------------ */
+
+/* First- (order 1, Eq. define-trotter) or second-order (order 2,
+ * symmetric: terms forward at delta/2 then reversed at delta/2) Trotter
+ * with delta = t / steps; phi = delta * h (order 1) or (delta * h) * 0.5.
+ * reorder = SUFFIX sorts the terms first.  INVALID if steps < 1, order not
+ * 1 or 2, t not finite. */
+prx_status prx_sched_trotter(const prx_ham *ham, int order, double t, int steps,
+                             prx_reorder reorder, prx_sched **out);
+
+/* qDRIFT (Methods, "Hamiltonian simulation"): N terms drawn i.i.d. with
+ * p_j = |h_j| / lambda, angle sgn(h_j) * ((lambda * t) / N).  Draws use
+ * SplitMix64 seeded with `seed`: u = (next >> 11) * 2^-53 picks the first
+ * index whose left-to-right FP64 running sum of |h| exceeds u * lambda.
+ * INVALID if N < 1 or lambda = 0. */
+prx_status prx_sched_qdrift(const prx_ham *ham, double t, size_t N, uint64_t seed,
+                            prx_sched **out);
+
+/* Partially randomised product formula (Eq. hamil_split): D = the L_det
+ * terms of largest |h| (ties to the lower index; original order, or sorted
+ * when reorder = SUFFIX), R = the rest in original order.  Per step
+ * (delta = t / steps): D forward at (delta * h) * 0.5, then r_per_step
+ * qDRIFT draws from R at sgn(h) * ((lambda_R * delta) / r_per_step), then D
+ * reversed at (delta * h) * 0.5.  One SplitMix64 stream for the whole
+ * schedule.  INVALID if L_det > L, steps < 1, or R is non-empty with
+ * r_per_step = 0. */
+prx_status prx_sched_partial(const prx_ham *ham, size_t L_det, double t, int steps,
+                             size_t r_per_step, uint64_t seed, prx_reorder reorder,
+                             prx_sched **out);
+
+/* Wraps an explicit rotation list (host arrays of length M, copied). */
+prx_status prx_sched_from_rotations(int n, size_t M, const uint64_t *x, const uint64_t *z,
+                                    const double *phi, prx_sched **out);
+
+/* Borrowed views of a schedule's arrays, valid until prx_sched_destroy. */
+prx_status prx_sched_view(const prx_sched *s, int *n, size_t *M, const uint64_t **x,
+                          const uint64_t **z, const double **phi);
+void prx_sched_destroy(prx_sched *s);
+
+/* ------------------------------------------------------------------ */
+/* Plans: a schedule segmented into HBM passes with device tables.     */
+/* ------------------------------------------------------------------ */
+
+/* Optional planner settings; zero fields take defaults. */
+typedef struct {
+    int tile_qubits;     /* qubits held by one workgroup in the tile kernel (default per dtype) */
+    int chunk_rank;      /* rotations' X-span rank a thread holds in registers (default 4) */
+    int max_fuse;        /* max rotations per tile pass (default 64) */
+    int span_max;        /* max rotations per span pass (default: chunk_rank and repeats) */
+    int max_virtual;     /* max high-qubit XOR masks gathered into a tile (default 2) */
+    int renorm_every;    /* C64: renormalise in FP64 every k passes (default 1; -1 = never) */
+    int commuting;       /* 1: planner may swap adjacent commuting rotations (default 0) */
+} prx_plan_opts;
+
+/* Summary of a plan. */
+typedef struct {
+    size_t rotations;         /* rotations in [begin, end) */
+    size_t kernel_rotations;  /* rotations after splitting large angles (fused only) */
+    size_t passes;            /* HBM sweeps over the state */
+    size_t plain_passes;      /* single-rotation sweeps */
+    size_t span_passes;       /* span-kernel sweeps */
+    size_t tile_passes;       /* tile-kernel sweeps */
+    size_t workspace_bytes;   /* bytes prx_plan_execute needs */
+    double mean_fuse;         /* rotations per pass */
+    int tile_qubits, chunk_rank;
+} prx_plan_info;
+
+/* Segments rotations [begin, end) of `sched` for a 2^n state of `dtype`
+ * with kernel family `kernel`.  Host only; no device calls.  opts may be
+ * NULL.  INVALID if begin > end or end > M. UNSUPPORTED if n > 40. */
+prx_status prx_plan_create(const prx_sched *sched, int n, prx_dtype dtype, size_t begin,
+                           size_t end, prx_kernel kernel, const prx_plan_opts *opts,
+                           prx_plan **out);
+prx_status prx_plan_get_info(const prx_plan *plan, prx_plan_info *out);
+void prx_plan_destroy(prx_plan *plan);
+
+/* Copies the plan's tables into `ws` (device, >= workspace_bytes) on
+ * `stream`.  Must precede prx_plan_execute with the same workspace; the
+ * tables stay valid until the workspace is overwritten.  The host source
+ * stays owned by the plan, so the copy may be asynchronous. */
+prx_status prx_plan_upload(const prx_plan *plan, void *ws, size_t ws_bytes, void *stream);
+
+/* Enqueues every pass of the plan on `stream` (asynchronous).  psi is the
+ * state (device, 2^n of dtype), ws the uploaded workspace. */
+prx_status prx_plan_execute(const prx_plan *plan, void *psi, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* Plan inspection (read-only views for tests and tools).
+ *
+ * Passes: kind 0 = single-rotation sweep, 1 = span pass (one chunk in the
+ * global index frame, `basis`/`pivot` valid), 2 = tile pass (workgroup
+ * frame of B bits = b low qubits + g virtual qubits; workgroup w holds the
+ * tiles (t XOR vcomb[v]) for v < 2^g, t = w with zeros inserted at the
+ * ascending `tpivot` bits of the tile index; chunks [chunk_begin, +count)).
+ * `scale` is the product of the pass's cosines, applied at its store. */
+typedef struct {
+    int kind;
+    size_t rot_begin, rot_count;      /* kernel rotations of the pass */
+    size_t chunk_begin, chunk_count;  /* tile passes */
+    int B, b, g, m;                   /* tile qubits, low qubits, virtual qubits, rank */
+    uint64_t basis[6];                /* span: X-mask basis (global frame) */
+    uint32_t pivot[6];                /* span: ascending pivot bits of its echelon form */
+    uint64_t vcomb[8];                /* tile: XOR of virtual masks per combination */
+    uint32_t tpivot[3];               /* tile: ascending pivot bits in tile-index space */
+    double scale;
+    int norm_out, renorm_in;          /* C64 renormalisation hand-off */
+} prx_pass_info;
+
+/* A chunk of a tile pass: basis directions in the workgroup frame and the
+ * ascending pivot bits used to enumerate coset representatives. */
+typedef struct {
+    uint32_t basis[6];
+    uint32_t pivot[6];
+    size_t rot_begin, rot_count;
+} prx_chunk_info;
+
+/* A kernel rotation: (x, z, phi) as applied (a rotation with |cos phi| <
+ * 1/2 appears as two half-angle rotations in fused plans), its schedule
+ * index, and its record: z in the kernel's frame, the tile-index part
+ * zhigh, basis slot (15 = diagonal), whether tau is imaginary, zeta
+ * (bit i = parity(basis_i & z)) and the signed magnitude of tau. */
+typedef struct {
+    uint64_t x, z;
+    double phi;
+    size_t source;
+    uint64_t zframe, zhigh;
+    uint32_t slot, imag, zeta;
+    double tau;
+} prx_rot_info;
+
+prx_status prx_plan_pass(const prx_plan *plan, size_t i, prx_pass_info *out);
+prx_status prx_plan_chunk(const prx_plan *plan, size_t i, prx_chunk_info *out);
+prx_status prx_plan_rotation(const prx_plan *plan, size_t i, prx_rot_info *out);
+
+/* ------------------------------------------------------------------ */
+/* One-call application and reductions.                                */
+/* ------------------------------------------------------------------ */
+
+/* Workspace bytes prx_apply_range needs for the whole schedule. */
+size_t prx_workspace_bytes(int n, prx_dtype dtype, const prx_sched *sched, prx_kernel kernel);
+
+/* Plans, uploads and executes rotations [begin, end) on psi, then waits
+ * for the stream (the host tables must outlive the copy).  Resuming from
+ * any rotation index with a second call gives the same product. */
+prx_status prx_apply_range(void *psi, int n, prx_dtype dtype, const prx_sched *sched,
+                           size_t begin, size_t end, prx_kernel kernel, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* Workspace bytes the reductions need for a 2^n state. */
+size_t prx_reduce_workspace_bytes(int n);
+
+/* out_re_im = <psi0|psi> = sum_k conj(psi0[k]) psi[k] (Methods, "Data
+ * analysis", the signal g(t)), accumulated in FP64 with compensated
+ * per-thread sums and a fixed-shape tree (deterministic).  Synchronises
+ * the stream. */
+prx_status prx_overlap(const void *psi0, const void *psi, int n, prx_dtype dtype,
+                       double out_re_im[2], void *ws, size_t ws_bytes, void *stream);
+
+/* out_re_im = <k|psi> = psi[k] widened to FP64.  Synchronises. */
+prx_status prx_amplitude(const void *psi, int n, prx_dtype dtype, uint64_t k,
+                         double out_re_im[2], void *stream);
+
+/* out = sum_k |psi[k]|^2 in FP64 (as prx_overlap).  Synchronises. */
+prx_status prx_norm2(const void *psi, int n, prx_dtype dtype, double *out, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/* psi <- psi / sqrt(norm2(psi)), the scale computed in FP64.  Synchronises. */
+prx_status prx_renormalize(void *psi, int n, prx_dtype dtype, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Batched samples in one persistent launch.                           */
+/* ------------------------------------------------------------------ */
+
+typedef struct prx_batch prx_batch;
+
+/* Plans S independent runs: sample s applies sched[s] to the state psi[s]
+ * (device, 2^n[s] of dtype; distinct, non-overlapping buffers) and reports
+ * <basis_idx[s]|psi_s>.  All samples run in one persistent kernel launch
+ * that pulls (sample, pass, slice) work items from a queue; per-sample
+ * counters order the passes of each sample.  Host only; no device calls.
+ * INVALID if S = 0, an n[s] is outside [6, 34], or basis_idx[s] >= 2^n[s]. */
+prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sched,
+                            prx_dtype dtype, const uint64_t *basis_idx, prx_batch **out);
+size_t prx_batch_workspace_bytes(const prx_batch *b);
+/* Uploads the tables, like prx_plan_upload. */
+prx_status prx_batch_upload(const prx_batch *b, void *ws, size_t ws_bytes, void *stream);
+/* Enqueues the persistent launch and the overlap read-out (asynchronous).
+ * psi[s] are device pointers (host array of S).  Resets the queue itself,
+ * so it may be replayed, including from a captured graph.  overlaps_dev is
+ * a device array of 2*S doubles receiving (re, im) per sample. */
+prx_status prx_batch_execute(const prx_batch *b, void *const *psi, void *ws, size_t ws_bytes,
+                             double *overlaps_dev, void *stream);
+void prx_batch_destroy(prx_batch *b);
+
+/* One-call form: create, upload, execute, copy the 2*S overlaps to the
+ * host array `overlaps`, synchronise, destroy. */
+prx_status prx_batch_run(size_t S, void *const *psi, const int *n,
+                         const prx_sched *const *sched, prx_dtype dtype,
+                         const uint64_t *basis_idx, double *overlaps, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Autotuning.                                                         */
+/* ------------------------------------------------------------------ */
+
+/* Times candidate (tile_qubits, chunk_rank, max_fuse) settings of the
+ * fused planner on `sched` applied to psi (whose contents are destroyed),
+ * and records the fastest for (n, dtype) in the in-process cache used by
+ * PRX_AUTO.  trials_out (nullable) receives the number of settings timed.
+ * Synchronises. */
+prx_status prx_autotune(void *psi, int n, prx_dtype dtype, const prx_sched *sched, void *ws,
+                        size_t ws_bytes, void *stream, prx_plan_opts *best_out,
+                        int *trials_out);
+/* Reads/writes the autotune cache as JSON text ({"gfx950/n/dtype": {...}}). */
+prx_status prx_autotune_save(const char *path);
+prx_status prx_autotune_load(const char *path);
+/* Returns the cached settings for (n, dtype), or UNSUPPORTED if absent. */
+prx_status prx_autotune_lookup(int n, prx_dtype dtype, prx_plan_opts *out);
+
+/* ------------------------------------------------------------------ */
+/* Diagnostics.                                                        */
+/* ------------------------------------------------------------------ */
+
+/* Thread-local description of the last failure on this thread. */
+const char *prx_last_error(void);
+/* Library version string. */
+const char *prx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRX_H */

@@ -1,0 +1,124 @@
+// Internal declarations shared by the host planner (host.cpp) and the HIP
+// kernels (kernels.hip, batch.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "prx.h"
+
+namespace prx {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+prx_status fail(prx_status st, const std::string &msg);
+prx_status hip_fail(hipError_t e, const char *what);
+
+#define PRX_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return ::prx::hip_fail(e_, #call);       \
+    } while (0)
+
+// ------------------------------------------------------- device tables
+//
+// One record per rotation of a fused (span or tile) pass.  The rotation
+// exp(i phi P) is applied in the factored form
+//     new[k] = cos(phi) * ( psi[k] + tau * sigma(k') * psi[k'] ),
+// k' = k XOR x, sigma(j) = (-1)^{popcount(j & z)}, tau = i^{nY+1} tan(phi)
+// (nY = popcount(x & z)); the cos(phi) factors of a pass are multiplied
+// into one scale applied when the pass stores the state.  For x = 0 the
+// partner is k itself.
+//
+//   z      : z mask in the frame the kernel indexes (span: global index;
+//            tile: workgroup-local index)
+//   zhigh  : tile only: z restricted to the tile-index bits, for the sign
+//            contributed by the workgroup's base tile
+//   info   : bits 0-3  basis slot of x in the chunk (15 = diagonal, x = 0)
+//            bit  4    tau is imaginary (nY + 1 odd)
+//            bits 8-15 zeta: bit i = parity(basis_i & z)
+//   tau    : signed magnitude of tau (real or imaginary part)
+template <typename T>
+struct RotRec {
+    uint64_t z;
+    uint64_t zhigh;
+    uint32_t info;
+    uint32_t pad;
+    T tau;
+};
+
+static constexpr uint32_t kSlotDiag = 15;
+static constexpr int kMaxChunkRank = 6;
+static constexpr int kMaxVirtual = 3;
+
+// A chunk of a tile pass: up to kMaxChunkRank basis directions in the
+// workgroup-local frame, with their pivot bits (reduced echelon form,
+// ascending) used to enumerate coset representatives, and a run of
+// rotations whose x masks are basis directions (or zero).
+struct ChunkRec {
+    uint32_t rot_begin;
+    uint32_t rot_count;
+    uint32_t basis[kMaxChunkRank];
+    uint8_t pivot[kMaxChunkRank];
+    uint8_t pad[2];
+};
+
+// Kernel arguments of a span pass (one chunk in the global frame).
+struct SpanArgs {
+    uint64_t basis[kMaxChunkRank];
+    uint32_t pivot[kMaxChunkRank];
+    uint32_t rot_begin, rot_count;
+    int n;
+    double scale;  // product of the pass's cosines
+};
+
+// Kernel arguments of a tile pass.
+struct TileArgs {
+    uint64_t vcomb[1 << kMaxVirtual];  // XOR of the virtual masks selected by each combination
+    uint32_t tpivot[kMaxVirtual];      // pivot bits (tile-index space) of the echelon virtual masks
+    int n, b, g;
+    uint32_t chunk_begin, chunk_count;
+    double scale;
+};
+
+// Arguments of a single-rotation sweep.
+struct PlainArgs {
+    uint64_t x, z;
+    int n;
+    int pivot;       // highest set bit of x (pair kernels)
+    int nY_odd;      // popcount(x & z) odd
+    int beta_imag;   // beta = i^{nY+1} sin(phi) is imaginary
+    double c;        // cos(phi)
+    double beta;     // signed magnitude of beta
+};
+
+// ------------------------------------------------------------ launchers
+// All enqueue on `stream` and return hipGetLastError() of the launch.
+hipError_t launch_plain(prx_dtype dt, void *psi, const PlainArgs &a, hipStream_t s);
+hipError_t launch_span(prx_dtype dt, int m, void *psi, const SpanArgs &a, const void *rots,
+                       const double *renorm_in, double *norm_out, hipStream_t s,
+                       unsigned *blocks_out);
+hipError_t launch_tile(prx_dtype dt, int B, int m, void *psi, const TileArgs &a,
+                       const void *rots, const ChunkRec *chunks, const double *renorm_in,
+                       double *norm_out, hipStream_t s, unsigned *blocks_out);
+// partial sums -> 1/sqrt(sum) into *scale_out (single block, fixed shape)
+hipError_t launch_renorm_finish(const double *partials, unsigned count, double *scale_out,
+                                hipStream_t s);
+unsigned span_blocks(int n, int m);
+unsigned tile_blocks(int n, int B);
+bool span_supported(prx_dtype dt, int m);
+bool tile_supported(prx_dtype dt, int B, int m);
+
+// Reductions.  `ws` holds kReduceBlocks * 2 doubles of partials plus 4
+// doubles of result.
+static constexpr unsigned kReduceBlocks = 1024;
+hipError_t launch_overlap(prx_dtype dt, const void *psi0, const void *psi, int n, double *ws,
+                          hipStream_t s);
+hipError_t launch_norm2(prx_dtype dt, const void *psi, int n, double *ws, hipStream_t s);
+hipError_t launch_scale(prx_dtype dt, void *psi, int n, const double *scale_dev,
+                        hipStream_t s);
+
+}  // namespace prx

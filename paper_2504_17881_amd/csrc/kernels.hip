@@ -1,0 +1,610 @@
+// HIP kernels for gfx950 (CDNA4, wave64): Pauli-rotation sweeps over a
+// 2^n complex state in HBM, and FP64 reductions.
+//
+// A rotation exp(i phi P) with P = (x, z) maps each index pair (k, k ^ x)
+// through a 2x2 unitary (paper, "Software implementation": the rotation is a
+// direct sum of 2x2 blocks, so (i) a permutation with phases by P and (ii) a
+// linear combination):
+//     new[k]  = cos(phi) psi[k]  + beta * sigma(k') psi[k']
+//     new[k'] = cos(phi) psi[k'] + beta * sigma(k)  psi[k]
+// with beta = i^{nY+1} sin(phi), nY = popcount(x & z) (the Y count, mod 4),
+// sigma(j) = (-1)^{popcount(j & z)} taken from the source index, and
+// sigma(k') = sigma(k) (-1)^{nY} (Supplementary Methods, "Pauli-string bit
+// representation").  For x = 0 the rotation is diagonal:
+// new[k] = (cos(phi) + i sin(phi) sigma(k)) psi[k].
+//
+// Kernels:
+//   k_plain_pair / k_plain_diag : one rotation per HBM sweep.
+//   k_span  : several consecutive rotations per sweep; every thread owns one
+//             coset k0 XOR span(x_1..x_m) of the rotations' X masks and keeps
+//             its 2^m amplitudes in registers.
+//   k_tile  : one workgroup owns a tile-set of 2^B amplitudes (2^g tiles of
+//             2^b contiguous amplitudes, g high-qubit XOR masks "virtual
+//             qubits") held in LDS; the pass's rotations run in chunks, each
+//             chunk gathered per thread as a coset of its X span.  The g = 1
+//             case is the single-GPU form of the common-suffix grouping of
+//             Eq. (core): all rotations sharing the high part of x are applied
+//             while the two partner tiles are resident.
+// Fused kernels use the factored update new = cos(phi) (psi + tau sigma
+// psi'), tau = beta / cos(phi); a pass multiplies its cosines (and an FP64
+// renormalisation factor) into one scale applied at the store.
+
+#include "internal.h"
+
+namespace prx {
+
+template <typename T>
+struct Cx {
+    T re, im;
+};
+
+__device__ __forceinline__ uint64_t insert_zero64(uint64_t v, uint32_t p) {
+    const uint64_t lo = v & ((1ull << p) - 1ull);
+    return ((v >> p) << (p + 1)) | lo;
+}
+__device__ __forceinline__ uint32_t insert_zero32(uint32_t v, uint32_t p) {
+    const uint32_t lo = v & ((1u << p) - 1u);
+    return ((v >> p) << (p + 1)) | lo;
+}
+__device__ __forceinline__ uint32_t parity64(uint64_t v) { return __popcll(v) & 1u; }
+
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Keeps a value materialised in a register, so that later sign flips of it
+// are single XORs instead of being re-derived from their inputs.
+__device__ __forceinline__ float pin(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ double pin(double v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Flip the sign of v when bit 0 of p is set (an XOR on the sign bit).
+__device__ __forceinline__ float flip(float v, uint32_t p) {
+    return __uint_as_float(__float_as_uint(v) ^ (p << 31));
+}
+__device__ __forceinline__ double flip(double v, uint32_t p) {
+    return __longlong_as_double(__double_as_longlong(v) ^ ((uint64_t)p << 63));
+}
+
+// ----------------------------------------------------------------- plain
+
+template <typename T, int U>
+__global__ void __launch_bounds__(256) k_plain_pair(Cx<T> *__restrict__ psi, PlainArgs a,
+                                                    uint64_t npairs) {
+    const T c = (T)a.c;
+    const T be = (T)a.beta;
+    const uint64_t base = (uint64_t)blockIdx.x * (256u * U) + threadIdx.x;
+    uint64_t k[U], kp[U];
+    Cx<T> u[U], w[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const uint64_t j = base + (uint64_t)i * 256u;
+        k[i] = insert_zero64(j < npairs ? j : 0, a.pivot);
+        kp[i] = k[i] ^ a.x;
+        if (j < npairs) {
+            u[i] = psi[k[i]];
+            w[i] = psi[kp[i]];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const uint64_t j = base + (uint64_t)i * 256u;
+        if (j >= npairs) continue;
+        const uint32_t sk = parity64(k[i] & a.z);
+        const T bk = flip(be, sk ^ (uint32_t)a.nY_odd);  // beta sigma(k'), used for new[k]
+        const T bkp = flip(be, sk);                      // beta sigma(k),  used for new[k']
+        Cx<T> nu, nw;
+        if (a.beta_imag) {
+            nu.re = c * u[i].re - bk * w[i].im;
+            nu.im = c * u[i].im + bk * w[i].re;
+            nw.re = c * w[i].re - bkp * u[i].im;
+            nw.im = c * w[i].im + bkp * u[i].re;
+        } else {
+            nu.re = c * u[i].re + bk * w[i].re;
+            nu.im = c * u[i].im + bk * w[i].im;
+            nw.re = c * w[i].re + bkp * u[i].re;
+            nw.im = c * w[i].im + bkp * u[i].im;
+        }
+        psi[k[i]] = nu;
+        psi[kp[i]] = nw;
+    }
+}
+
+template <typename T, int U>
+__global__ void __launch_bounds__(256) k_plain_diag(Cx<T> *__restrict__ psi, PlainArgs a,
+                                                    uint64_t N) {
+    const T c = (T)a.c;
+    const T s = (T)a.beta;  // beta = i sin(phi) for x = 0
+    const uint64_t base = (uint64_t)blockIdx.x * (256u * U) + threadIdx.x;
+    Cx<T> u[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const uint64_t k = base + (uint64_t)i * 256u;
+        if (k < N) u[i] = psi[k];
+    }
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const uint64_t k = base + (uint64_t)i * 256u;
+        if (k >= N) continue;
+        const T bs = flip(s, parity64(k & a.z));
+        Cx<T> nu;
+        nu.re = c * u[i].re - bs * u[i].im;
+        nu.im = c * u[i].im + bs * u[i].re;
+        psi[k] = nu;
+    }
+}
+
+// ------------------------------------------------------ register updates
+//
+// amp[v], v in [0, 2^M), holds the amplitude at k0 XOR X(v), X(v) the XOR
+// of the basis directions selected by v.  sigma(k0 XOR X(v)) =
+// sigma0 XOR parity(v & zeta).  A rotation whose x is basis direction I
+// pairs v with v | (1 << I).
+
+template <typename T, int M, int I, bool IMAG>
+__device__ __forceinline__ void rot_slot(Cx<T> (&amp)[1 << M], T g, uint32_t zeta) {
+#pragma unroll
+    for (int v = 0; v < (1 << M); ++v) {
+        if (v & (1 << I)) continue;
+        const int w = v | (1 << I);
+        const T gw = flip(g, (uint32_t)__builtin_popcount((uint32_t)w & zeta) & 1u);
+        const T gv = flip(g, (uint32_t)__builtin_popcount((uint32_t)v & zeta) & 1u);
+        const Cx<T> av = amp[v], aw = amp[w];
+        if (IMAG) {
+            amp[v].re = fmat(-gw, aw.im, av.re);
+            amp[v].im = fmat(gw, aw.re, av.im);
+            amp[w].re = fmat(-gv, av.im, aw.re);
+            amp[w].im = fmat(gv, av.re, aw.im);
+        } else {
+            amp[v].re = fmat(gw, aw.re, av.re);
+            amp[v].im = fmat(gw, aw.im, av.im);
+            amp[w].re = fmat(gv, av.re, aw.re);
+            amp[w].im = fmat(gv, av.im, aw.im);
+        }
+    }
+}
+
+// x = 0: new = psi (1 + i tau' sigma), tau' = tan(phi) (tau is imaginary).
+template <typename T, int M>
+__device__ __forceinline__ void rot_diag(Cx<T> (&amp)[1 << M], T g, uint32_t zeta) {
+#pragma unroll
+    for (int v = 0; v < (1 << M); ++v) {
+        const T gv = flip(g, (uint32_t)__builtin_popcount((uint32_t)v & zeta) & 1u);
+        const Cx<T> av = amp[v];
+        amp[v].re = fmat(-gv, av.im, av.re);
+        amp[v].im = fmat(gv, av.re, av.im);
+    }
+}
+
+template <typename T, int M, int I>
+__device__ __forceinline__ void rot_slot_any(Cx<T> (&amp)[1 << M], T g, uint32_t zeta,
+                                             bool imag) {
+    if (imag)
+        rot_slot<T, M, I, true>(amp, g, zeta);
+    else
+        rot_slot<T, M, I, false>(amp, g, zeta);
+}
+
+// Applies rotations [0, count) of `rots` to the thread's coset.
+// k0: coset representative in the frame of rec.z; tsign_base: the tile
+// index whose parity with rec.zhigh adds to the sign (0 for span passes).
+template <typename T, int M>
+__device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], uint64_t k0, uint64_t tbase,
+                                           const RotRec<T> *__restrict__ rots, uint32_t count) {
+    for (uint32_t r = 0; r < count; ++r) {
+        const RotRec<T> rec = rots[r];
+        const uint32_t s0 = parity64(k0 & rec.z) ^ parity64(tbase & rec.zhigh);
+        const T g = pin(flip(rec.tau, s0));
+        const uint32_t slot = rec.info & 15u;
+        const bool imag = (rec.info >> 4) & 1u;
+        const uint32_t zeta = (rec.info >> 8) & 0xffu;
+        switch (slot) {
+        case 0: rot_slot_any<T, M, 0>(amp, g, zeta, imag); break;
+        case 1: if constexpr (M > 1) rot_slot_any<T, M, 1>(amp, g, zeta, imag); break;
+        case 2: if constexpr (M > 2) rot_slot_any<T, M, 2>(amp, g, zeta, imag); break;
+        case 3: if constexpr (M > 3) rot_slot_any<T, M, 3>(amp, g, zeta, imag); break;
+        case 4: if constexpr (M > 4) rot_slot_any<T, M, 4>(amp, g, zeta, imag); break;
+        case 5: if constexpr (M > 5) rot_slot_any<T, M, 5>(amp, g, zeta, imag); break;
+        default: rot_diag<T, M>(amp, g, zeta); break;
+        }
+    }
+}
+
+// FP64 block sum of one value per thread; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if constexpr (NT > 64) {
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int i = 0; i < NT / 64; ++i) s += red[i];
+            v = s;
+        }
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ span
+
+template <typename T, int M>
+__global__ void __launch_bounds__(256) k_span(Cx<T> *__restrict__ psi, SpanArgs a,
+                                              const RotRec<T> *__restrict__ rots,
+                                              const double *__restrict__ renorm_in,
+                                              double *__restrict__ norm_out) {
+    __shared__ double red[4];
+    const uint64_t ncos = 1ull << (a.n - M);
+    const uint64_t t = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    const bool live = t < ncos;
+    uint64_t k0 = live ? t : 0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) k0 = insert_zero64(k0, a.pivot[i]);
+    uint64_t X[1 << M];
+    X[0] = 0;
+#pragma unroll
+    for (int v = 1; v < (1 << M); ++v) X[v] = X[v & (v - 1)] ^ a.basis[__builtin_ctz(v)];
+    Cx<T> amp[1 << M];
+    if (live) {
+#pragma unroll
+        for (int v = 0; v < (1 << M); ++v) amp[v] = psi[k0 ^ X[v]];
+    }
+    apply_rots<T, M>(amp, k0, 0, rots + a.rot_begin, a.rot_count);
+    double sc = a.scale;
+    if (renorm_in) sc *= *renorm_in;
+    const T s = (T)sc;
+    double nrm = 0.0;
+    if (live) {
+#pragma unroll
+        for (int v = 0; v < (1 << M); ++v) {
+            Cx<T> o;
+            o.re = amp[v].re * s;
+            o.im = amp[v].im * s;
+            psi[k0 ^ X[v]] = o;
+            nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+        }
+    }
+    if (norm_out) {
+        nrm = block_sum<256>(nrm, red);
+        if (threadIdx.x == 0) norm_out[blockIdx.x] = nrm;
+    }
+}
+
+// ------------------------------------------------------------------ tile
+
+template <typename T, int B, int M>
+__global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, TileArgs a,
+                                                      const RotRec<T> *__restrict__ rots,
+                                                      const ChunkRec *__restrict__ chunks,
+                                                      const double *__restrict__ renorm_in,
+                                                      double *__restrict__ norm_out) {
+    constexpr int NT = 1 << (B - M);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Cx<T> *lds = reinterpret_cast<Cx<T> *>(lds_raw);
+    __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+    const uint32_t tid = threadIdx.x;
+
+    uint64_t tb = blockIdx.x;
+    for (int i = 0; i < a.g; ++i) tb = insert_zero64(tb, a.tpivot[i]);
+    const int b = a.b;
+    const uint32_t tile_len = 1u << b;
+    const int ncomb = 1 << a.g;
+
+    for (int vb = 0; vb < ncomb; ++vb) {
+        const Cx<T> *src = psi + ((tb ^ a.vcomb[vb]) << b);
+        Cx<T> *dst = lds + ((uint32_t)vb << b);
+        for (uint32_t off = tid; off < tile_len; off += NT) dst[off] = src[off];
+    }
+    __syncthreads();
+
+    for (uint32_t c = 0; c < a.chunk_count; ++c) {
+        const ChunkRec ch = chunks[a.chunk_begin + c];
+        uint32_t k0 = tid;
+#pragma unroll
+        for (int i = 0; i < M; ++i) k0 = insert_zero32(k0, ch.pivot[i]);
+        uint32_t X[1 << M];
+        X[0] = 0;
+#pragma unroll
+        for (int v = 1; v < (1 << M); ++v) X[v] = X[v & (v - 1)] ^ ch.basis[__builtin_ctz(v)];
+        Cx<T> amp[1 << M];
+#pragma unroll
+        for (int v = 0; v < (1 << M); ++v) amp[v] = lds[k0 ^ X[v]];
+        apply_rots<T, M>(amp, k0, tb, rots + ch.rot_begin, ch.rot_count);
+#pragma unroll
+        for (int v = 0; v < (1 << M); ++v) lds[k0 ^ X[v]] = amp[v];
+        __syncthreads();
+    }
+
+    double sc = a.scale;
+    if (renorm_in) sc *= *renorm_in;
+    const T s = (T)sc;
+    double nrm = 0.0;
+    for (int vb = 0; vb < ncomb; ++vb) {
+        Cx<T> *dst = psi + ((tb ^ a.vcomb[vb]) << b);
+        const Cx<T> *src = lds + ((uint32_t)vb << b);
+        for (uint32_t off = tid; off < tile_len; off += NT) {
+            Cx<T> o = src[off];
+            o.re *= s;
+            o.im *= s;
+            dst[off] = o;
+            nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+        }
+    }
+    if (norm_out) {
+        nrm = block_sum<NT>(nrm, red);
+        if (tid == 0) norm_out[blockIdx.x] = nrm;
+    }
+}
+
+// ------------------------------------------------------------ reductions
+
+// Neumaier-compensated accumulator.
+struct Neu {
+    double s = 0.0, c = 0.0;
+    __device__ __forceinline__ void add(double v) {
+        const double t = s + v;
+        if (fabs(s) >= fabs(v))
+            c += (s - t) + v;
+        else
+            c += (v - t) + s;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return s + c; }
+};
+
+// Fixed-shape tree over the block (deterministic for a fixed launch shape).
+__device__ __forceinline__ double tree256(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < (unsigned)w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_overlap(const Cx<T> *__restrict__ a,
+                                                 const Cx<T> *__restrict__ b, uint64_t N,
+                                                 double *__restrict__ part) {
+    __shared__ double sh[256];
+    Neu re, im;
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    for (uint64_t k = (uint64_t)blockIdx.x * 256u + threadIdx.x; k < N; k += stride) {
+        const Cx<T> u = a[k], v = b[k];
+        // conj(u) * v
+        re.add((double)u.re * (double)v.re);
+        re.add((double)u.im * (double)v.im);
+        im.add((double)u.re * (double)v.im);
+        im.add(-(double)u.im * (double)v.re);
+    }
+    const double r = tree256(re.value(), sh);
+    const double i = tree256(im.value(), sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = r;
+        part[2 * blockIdx.x + 1] = i;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_norm2(const Cx<T> *__restrict__ a, uint64_t N,
+                                               double *__restrict__ part) {
+    __shared__ double sh[256];
+    Neu acc;
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    for (uint64_t k = (uint64_t)blockIdx.x * 256u + threadIdx.x; k < N; k += stride) {
+        const Cx<T> u = a[k];
+        acc.add((double)u.re * (double)u.re);
+        acc.add((double)u.im * (double)u.im);
+    }
+    const double r = tree256(acc.value(), sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = r;
+        part[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+// Sums `count` (re, im) partials into out[0..1] with one 256-thread block.
+__global__ void __launch_bounds__(256) k_finish_pairs(const double *__restrict__ part,
+                                                      unsigned count, double *__restrict__ out) {
+    __shared__ double sh[256];
+    Neu re, im;
+    for (unsigned i = threadIdx.x; i < count; i += 256u) {
+        re.add(part[2 * i]);
+        im.add(part[2 * i + 1]);
+    }
+    const double r = tree256(re.value(), sh);
+    const double m = tree256(im.value(), sh);
+    if (threadIdx.x == 0) {
+        out[0] = r;
+        out[1] = m;
+    }
+}
+
+// Sums `count` norm partials and writes 1/sqrt(sum).
+__global__ void __launch_bounds__(256) k_renorm_finish(const double *__restrict__ part,
+                                                       unsigned count,
+                                                       double *__restrict__ scale_out) {
+    __shared__ double sh[256];
+    Neu acc;
+    for (unsigned i = threadIdx.x; i < count; i += 256u) acc.add(part[i]);
+    const double s = tree256(acc.value(), sh);
+    if (threadIdx.x == 0) scale_out[0] = 1.0 / sqrt(s);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_scale(Cx<T> *__restrict__ a, uint64_t N,
+                                               const double *__restrict__ scale) {
+    const T s = (T)scale[0];
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    for (uint64_t k = (uint64_t)blockIdx.x * 256u + threadIdx.x; k < N; k += stride) {
+        Cx<T> u = a[k];
+        u.re *= s;
+        u.im *= s;
+        a[k] = u;
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+static unsigned ceil_div_u(uint64_t a, uint64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <typename T>
+static hipError_t plain_t(void *psi, const PlainArgs &a, hipStream_t s) {
+    constexpr int U = 4;
+    if (a.x == 0) {
+        const uint64_t N = 1ull << a.n;
+        hipLaunchKernelGGL((k_plain_diag<T, U>), dim3(ceil_div_u(N, 256u * U)), dim3(256), 0, s,
+                           (Cx<T> *)psi, a, N);
+    } else {
+        const uint64_t np = 1ull << (a.n - 1);
+        hipLaunchKernelGGL((k_plain_pair<T, U>), dim3(ceil_div_u(np, 256u * U)), dim3(256), 0, s,
+                           (Cx<T> *)psi, a, np);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plain(prx_dtype dt, void *psi, const PlainArgs &a, hipStream_t s) {
+    return dt == PRX_C64 ? plain_t<float>(psi, a, s) : plain_t<double>(psi, a, s);
+}
+
+unsigned span_blocks(int n, int m) { return ceil_div_u(1ull << (n - m), 256u); }
+unsigned tile_blocks(int n, int B) { return (unsigned)(1ull << (n - B)); }
+
+bool span_supported(prx_dtype, int m) { return m >= 1 && m <= 5; }
+
+template <typename T>
+static hipError_t span_t(int m, void *psi, const SpanArgs &a, const void *rots,
+                         const double *rin, double *nout, hipStream_t s, unsigned *blocks) {
+    const unsigned nb = span_blocks(a.n, m);
+    *blocks = nb;
+    const RotRec<T> *r = (const RotRec<T> *)rots;
+    Cx<T> *p = (Cx<T> *)psi;
+    switch (m) {
+    case 1: hipLaunchKernelGGL((k_span<T, 1>), dim3(nb), dim3(256), 0, s, p, a, r, rin, nout); break;
+    case 2: hipLaunchKernelGGL((k_span<T, 2>), dim3(nb), dim3(256), 0, s, p, a, r, rin, nout); break;
+    case 3: hipLaunchKernelGGL((k_span<T, 3>), dim3(nb), dim3(256), 0, s, p, a, r, rin, nout); break;
+    case 4: hipLaunchKernelGGL((k_span<T, 4>), dim3(nb), dim3(256), 0, s, p, a, r, rin, nout); break;
+    case 5: hipLaunchKernelGGL((k_span<T, 5>), dim3(nb), dim3(256), 0, s, p, a, r, rin, nout); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_span(prx_dtype dt, int m, void *psi, const SpanArgs &a, const void *rots,
+                       const double *renorm_in, double *norm_out, hipStream_t s,
+                       unsigned *blocks_out) {
+    return dt == PRX_C64 ? span_t<float>(m, psi, a, rots, renorm_in, norm_out, s, blocks_out)
+                         : span_t<double>(m, psi, a, rots, renorm_in, norm_out, s, blocks_out);
+}
+
+// (B, M) pairs instantiated for the tile kernel.
+#define PRX_TILE_SHAPES(X) X(10, 3) X(10, 4) X(11, 4) X(12, 4) X(12, 5) X(13, 5)
+
+bool tile_supported(prx_dtype dt, int B, int m) {
+#define PRX_TS(BB, MM) if (B == BB && m == MM) return dt == PRX_C64 || BB <= 12;
+    PRX_TILE_SHAPES(PRX_TS)
+#undef PRX_TS
+    return false;
+}
+
+template <typename T, int B, int M>
+static hipError_t tile_launch_one(void *psi, const TileArgs &a, const void *rots,
+                                  const ChunkRec *chunks, const double *rin, double *nout,
+                                  hipStream_t s, unsigned *blocks) {
+    const size_t lds = sizeof(Cx<T>) << B;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_tile<T, B, M>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const unsigned nb = tile_blocks(a.n, B);
+    *blocks = nb;
+    hipLaunchKernelGGL((k_tile<T, B, M>), dim3(nb), dim3(1 << (B - M)), lds, s, (Cx<T> *)psi, a,
+                       (const RotRec<T> *)rots, chunks, rin, nout);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t tile_t(int B, int m, void *psi, const TileArgs &a, const void *rots,
+                         const ChunkRec *chunks, const double *rin, double *nout, hipStream_t s,
+                         unsigned *blocks) {
+#define PRX_TL(BB, MM)                                                                    \
+    if (B == BB && m == MM) {                                                             \
+        if constexpr (sizeof(T) == 4 || BB <= 12)                                         \
+            return tile_launch_one<T, BB, MM>(psi, a, rots, chunks, rin, nout, s, blocks); \
+        return hipErrorInvalidValue;                                                      \
+    }
+    PRX_TILE_SHAPES(PRX_TL)
+#undef PRX_TL
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile(prx_dtype dt, int B, int m, void *psi, const TileArgs &a,
+                       const void *rots, const ChunkRec *chunks, const double *renorm_in,
+                       double *norm_out, hipStream_t s, unsigned *blocks_out) {
+    return dt == PRX_C64
+               ? tile_t<float>(B, m, psi, a, rots, chunks, renorm_in, norm_out, s, blocks_out)
+               : tile_t<double>(B, m, psi, a, rots, chunks, renorm_in, norm_out, s, blocks_out);
+}
+
+hipError_t launch_renorm_finish(const double *partials, unsigned count, double *scale_out,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_renorm_finish, dim3(1), dim3(256), 0, s, partials, count, scale_out);
+    return hipGetLastError();
+}
+
+static unsigned reduce_grid(uint64_t N) {
+    const uint64_t want = (N + 256u * 8u - 1) / (256u * 8u);
+    return (unsigned)(want < kReduceBlocks ? (want ? want : 1) : kReduceBlocks);
+}
+
+hipError_t launch_overlap(prx_dtype dt, const void *psi0, const void *psi, int n, double *ws,
+                          hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    const unsigned g = reduce_grid(N);
+    if (dt == PRX_C64)
+        hipLaunchKernelGGL(k_overlap<float>, dim3(g), dim3(256), 0, s, (const Cx<float> *)psi0,
+                           (const Cx<float> *)psi, N, ws);
+    else
+        hipLaunchKernelGGL(k_overlap<double>, dim3(g), dim3(256), 0, s, (const Cx<double> *)psi0,
+                           (const Cx<double> *)psi, N, ws);
+    hipLaunchKernelGGL(k_finish_pairs, dim3(1), dim3(256), 0, s, ws, g, ws + 2 * kReduceBlocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2(prx_dtype dt, const void *psi, int n, double *ws, hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    const unsigned g = reduce_grid(N);
+    if (dt == PRX_C64)
+        hipLaunchKernelGGL(k_norm2<float>, dim3(g), dim3(256), 0, s, (const Cx<float> *)psi, N, ws);
+    else
+        hipLaunchKernelGGL(k_norm2<double>, dim3(g), dim3(256), 0, s, (const Cx<double> *)psi, N,
+                           ws);
+    hipLaunchKernelGGL(k_finish_pairs, dim3(1), dim3(256), 0, s, ws, g, ws + 2 * kReduceBlocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(prx_dtype dt, void *psi, int n, const double *scale_dev,
+                        hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    const unsigned g = (unsigned)std::min<uint64_t>((N + 255) / 256, 256u * 64u);
+    if (dt == PRX_C64)
+        hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(256), 0, s, (Cx<float> *)psi, N, scale_dev);
+    else
+        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(256), 0, s, (Cx<double> *)psi, N,
+                           scale_dev);
+    return hipGetLastError();
+}
+
+}  // namespace prx

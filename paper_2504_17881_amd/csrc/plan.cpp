@@ -1,0 +1,835 @@
+// Planner: segments a rotation list into HBM passes and builds the device
+// tables; executor: enqueues the passes; one-call apply and reductions.
+//
+// Segmentation (greedy, in application order):
+//   * span pass: consecutive rotations whose X masks are repeats of, or
+//     linearly independent additions to, a basis of at most `span_m`
+//     masks (x = 0 rotations always fit).  Each thread owns one coset of the
+//     basis span, so the pass applies them all in registers with one read
+//     and one write of the state.
+//   * tile pass: consecutive rotations whose X masks lie in a tile frame of
+//     B qubits: the low b = B - g qubits plus g "virtual" qubits, each an XOR
+//     mask of high (tile-index) bits.  A workgroup holds the 2^g tiles
+//     t XOR span(masks) in LDS.  The g = 1 case keeps the two tiles paired by
+//     a shared high X part resident, which is the single-GPU form of the
+//     common-suffix grouping of Eq. (core); g = 0 holds rotations acting on
+//     low qubits only (local operations, Supplementary Methods).
+//   * plain pass: a single rotation (pair or diagonal sweep).
+// With `commuting` on, a rotation that does not fit may be replaced by a
+// later one that does, if that one commutes with every rotation it moves
+// ahead of (an exact reordering).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "objects.h"
+
+namespace prx {
+
+static inline int popc(uint64_t v) { return __builtin_popcountll(v); }
+static inline uint32_t par(uint64_t v) { return (uint32_t)(__builtin_popcountll(v) & 1); }
+static inline int hibit(uint64_t v) { return 63 - __builtin_clzll(v); }
+static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static inline bool commute(const KRot &a, const KRot &b) {
+    return (popc((a.x & b.z) ^ (a.z & b.x)) & 1) == 0;
+}
+
+// Row-echelon basis over GF(2) with pivot = highest set bit of each row;
+// every row remembers which of the inserted vectors it combines.
+struct Gf2 {
+    std::vector<uint64_t> orig;
+    std::vector<uint64_t> row, comb;
+    // reduce v; returns the remainder and the combination of originals used
+    uint64_t reduce(uint64_t v, uint64_t *cmb) const {
+        uint64_t c = 0;
+        bool again = true;
+        while (v && again) {
+            again = false;
+            for (size_t i = 0; i < row.size(); ++i) {
+                if (hibit(row[i]) == hibit(v)) {
+                    v ^= row[i];
+                    c ^= comb[i];
+                    again = true;
+                    break;
+                }
+            }
+        }
+        if (cmb) *cmb = c;
+        return v;
+    }
+    bool contains(uint64_t v) const { return reduce(v, nullptr) == 0; }
+    // adds v (must be independent); returns its index among originals
+    size_t add(uint64_t v) {
+        uint64_t c;
+        uint64_t r = reduce(v, &c);
+        const size_t id = orig.size();
+        orig.push_back(v);
+        row.push_back(r);
+        comb.push_back(c ^ (1ull << id));
+        return id;
+    }
+    std::vector<uint32_t> pivots() const {
+        std::vector<uint32_t> p;
+        for (uint64_t r : row) p.push_back((uint32_t)hibit(r));
+        std::sort(p.begin(), p.end());
+        return p;
+    }
+    size_t rank() const { return orig.size(); }
+};
+
+// Tau and the info bits common to span and tile records.
+struct Coef {
+    double tau;
+    uint32_t imag;
+};
+static Coef fused_coef(const KRot &r) {
+    const double c = std::cos(r.phi), s = std::sin(r.phi);
+    const int mq = (popc(r.x & r.z) + 1) & 3;
+    Coef o;
+    o.tau = ((mq >= 2) ? -1.0 : 1.0) * (s / c);
+    o.imag = (uint32_t)(mq & 1);
+    return o;
+}
+
+static PlainArgs plain_args(int n, const KRot &r) {
+    PlainArgs a;
+    a.x = r.x;
+    a.z = r.z;
+    a.n = n;
+    a.pivot = r.x ? hibit(r.x) : 0;
+    const int nY = popc(r.x & r.z);
+    a.nY_odd = nY & 1;
+    const int mq = (nY + 1) & 3;
+    a.beta_imag = mq & 1;
+    a.c = std::cos(r.phi);
+    a.beta = ((mq >= 2) ? -1.0 : 1.0) * std::sin(r.phi);
+    return a;
+}
+
+// ---------------------------------------------------------------- planner
+
+struct Builder {
+    prx_plan &P;
+    std::vector<KRot> &R;
+    size_t end;
+    const PlanCfg &cfg;
+    std::vector<RotRecD> recs;  // double records; converted to the dtype at the end
+
+    Builder(prx_plan &p, size_t e) : P(p), R(p.rots), end(e), cfg(p.cfg) {}
+
+    // Length of the span run starting at p (no reordering).
+    size_t span_len(size_t p, int mmax) const {
+        Gf2 g;
+        std::vector<uint64_t> basis;
+        size_t j = p;
+        for (; j < end && (int)(j - p) < cfg.max_fuse; ++j) {
+            const uint64_t x = R[j].x;
+            if (x == 0 || std::find(basis.begin(), basis.end(), x) != basis.end()) continue;
+            if ((int)basis.size() < mmax && !g.contains(x)) {
+                g.add(x);
+                basis.push_back(x);
+                continue;
+            }
+            break;
+        }
+        return j - p;
+    }
+
+    bool tile_fits(uint64_t x, int b, Gf2 &M, int g, bool grow) const {
+        const uint64_t xh = x >> b;
+        if (xh == 0 || M.contains(xh)) return true;
+        if ((int)M.rank() < g) {
+            if (grow) M.add(xh);
+            return true;
+        }
+        return false;
+    }
+
+    size_t tile_len(size_t p, int g) const {
+        const int b = cfg.B - g;
+        Gf2 M;
+        size_t j = p;
+        for (; j < end && (int)(j - p) < cfg.max_fuse; ++j)
+            if (!tile_fits(R[j].x, b, M, g, true)) break;
+        return j - p;
+    }
+
+    // With commuting on: bring forward a later rotation that fits, if it
+    // commutes with all rotations it jumps over.  `fits` must not mutate.
+    template <class F>
+    bool pull_forward(size_t j, F fits) {
+        if (!cfg.commuting) return false;
+        const size_t lim = std::min(end, j + 32);
+        for (size_t k = j + 1; k < lim; ++k) {
+            if (!fits(R[k])) continue;
+            bool ok = true;
+            for (size_t i = j; i < k && ok; ++i) ok = commute(R[i], R[k]);
+            if (!ok) continue;
+            KRot t = R[k];
+            for (size_t i = k; i > j; --i) R[i] = R[i - 1];
+            R[j] = t;
+            return true;
+        }
+        return false;
+    }
+
+    void emit_plain(size_t p) {
+        Pass ps;
+        ps.kind = kPlain;
+        ps.r0 = p;
+        ps.r1 = p + 1;
+        P.passes.push_back(ps);
+        recs.push_back(RotRecD{});
+        P.plain_passes++;
+    }
+
+    size_t emit_span(size_t p) {
+        Gf2 g;
+        std::vector<uint64_t> basis;
+        size_t j = p;
+        auto fits = [&](const KRot &r) {
+            if (r.x == 0 || std::find(basis.begin(), basis.end(), r.x) != basis.end()) return true;
+            return (int)basis.size() < cfg.span_m && !g.contains(r.x);
+        };
+        for (; j < end && (int)(j - p) < cfg.max_fuse; ++j) {
+            if (!fits(R[j]) && !pull_forward(j, fits)) break;
+            const uint64_t x = R[j].x;
+            if (x && std::find(basis.begin(), basis.end(), x) == basis.end()) {
+                g.add(x);
+                basis.push_back(x);
+            }
+        }
+        if (basis.empty()) {  // diagonal-only run: any direction serves as the basis
+            basis.push_back(1);
+            g.add(1);
+        }
+        Pass ps;
+        ps.kind = kSpan;
+        ps.r0 = p;
+        ps.r1 = j;
+        ps.m = (int)basis.size();
+        auto piv = g.pivots();
+        for (int i = 0; i < ps.m; ++i) {
+            ps.basis[i] = basis[i];
+            ps.pivot[i] = piv[i];
+        }
+        double scale = 1.0;
+        for (size_t r = p; r < j; ++r) {
+            const KRot &k = R[r];
+            const Coef cf = fused_coef(k);
+            scale *= std::cos(k.phi);
+            uint32_t slot = kSlotDiag;
+            if (k.x) slot = (uint32_t)(std::find(basis.begin(), basis.end(), k.x) - basis.begin());
+            uint32_t zeta = 0;
+            for (int i = 0; i < ps.m; ++i) zeta |= par(basis[i] & k.z) << i;
+            RotRecD rr;
+            rr.z = k.z;
+            rr.zhigh = 0;
+            rr.info = slot | (cf.imag << 4) | (zeta << 8);
+            rr.tau = cf.tau;
+            recs.push_back(rr);
+        }
+        ps.scale = scale;
+        P.passes.push_back(ps);
+        P.span_passes++;
+        return j;
+    }
+
+    size_t emit_tile(size_t p, int g) {
+        const int b = cfg.B - g;
+        const uint64_t low = (b >= 64) ? ~0ull : ((1ull << b) - 1ull);
+        Gf2 M;
+        size_t j = p;
+        auto fits = [&](const KRot &r) {
+            Gf2 copy = M;
+            return tile_fits(r.x, b, copy, g, false);
+        };
+        for (; j < end && (int)(j - p) < cfg.max_fuse; ++j) {
+            if (!fits(R[j]) && !pull_forward(j, fits)) break;
+            tile_fits(R[j].x, b, M, g, true);
+        }
+        // Pad the virtual masks to exactly g with unused high unit vectors so
+        // that every workgroup holds 2^B amplitudes.
+        for (int q = P.n - b - 1; (int)M.rank() < g && q >= 0; --q)
+            if (!M.contains(1ull << q)) M.add(1ull << q);
+        Pass ps;
+        ps.kind = kTile;
+        ps.r0 = p;
+        ps.r1 = j;
+        ps.B = cfg.B;
+        ps.b = b;
+        ps.g = g;
+        ps.m = cfg.m;
+        for (int i = 0; i < g; ++i) ps.vmask[i] = M.orig[i];
+        for (int vb = 0; vb < (1 << g); ++vb) {
+            uint64_t v = 0;
+            for (int i = 0; i < g; ++i)
+                if (vb >> i & 1) v ^= M.orig[i];
+            ps.vcomb[vb] = v;
+        }
+        auto tp = M.pivots();
+        for (int i = 0; i < g; ++i) ps.tpivot[i] = tp[i];
+        ps.c0 = P.chunks.size();
+
+        // Map each rotation into the workgroup-local frame (B bits).
+        struct Loc {
+            uint32_t x, z;
+            uint64_t zhigh;
+        };
+        std::vector<Loc> loc(j - p);
+        for (size_t r = p; r < j; ++r) {
+            const KRot &k = R[r];
+            const uint64_t xh = k.x >> b, zh = k.z >> b;
+            uint64_t cmb = 0;
+            M.reduce(xh, &cmb);
+            uint32_t zv = 0;
+            for (int i = 0; i < g; ++i) zv |= par(M.orig[i] & zh) << i;
+            Loc L;
+            L.x = (uint32_t)(k.x & low) | (uint32_t)(cmb << b);
+            L.z = (uint32_t)(k.z & low) | (zv << b);
+            L.zhigh = zh;
+            loc[r - p] = L;
+        }
+        // Chunks: runs whose local X masks are repeats of, or independent
+        // additions to, a basis of rank <= m.
+        double scale = 1.0;
+        size_t r = p;
+        while (r < j) {
+            Gf2 cg;
+            std::vector<uint32_t> basis;
+            size_t q = r;
+            for (; q < j; ++q) {
+                const uint32_t x = loc[q - p].x;
+                if (x == 0 || std::find(basis.begin(), basis.end(), x) != basis.end()) continue;
+                if ((int)basis.size() < cfg.m && !cg.contains(x)) {
+                    cg.add(x);
+                    basis.push_back(x);
+                    continue;
+                }
+                break;
+            }
+            for (int u = cfg.B - 1; (int)basis.size() < cfg.m && u >= 0; --u) {
+                if (!cg.contains(1ull << u)) {
+                    cg.add(1ull << u);
+                    basis.push_back(1u << u);
+                }
+            }
+            ChunkRec ch;
+            std::memset(&ch, 0, sizeof(ch));
+            ch.rot_begin = (uint32_t)r;
+            ch.rot_count = (uint32_t)(q - r);
+            auto piv = cg.pivots();
+            for (int i = 0; i < cfg.m; ++i) {
+                ch.basis[i] = basis[i];
+                ch.pivot[i] = (uint8_t)piv[i];
+            }
+            P.chunks.push_back(ch);
+            for (size_t t = r; t < q; ++t) {
+                const KRot &k = R[t];
+                const Loc &L = loc[t - p];
+                const Coef cf = fused_coef(k);
+                scale *= std::cos(k.phi);
+                uint32_t slot = kSlotDiag;
+                if (L.x) slot = (uint32_t)(std::find(basis.begin(), basis.end(), L.x) - basis.begin());
+                uint32_t zeta = 0;
+                for (int i = 0; i < cfg.m; ++i) zeta |= par((uint64_t)basis[i] & L.z) << i;
+                RotRecD rr;
+                rr.z = L.z;
+                rr.zhigh = L.zhigh;
+                rr.info = slot | (cf.imag << 4) | (zeta << 8);
+                rr.tau = cf.tau;
+                recs.push_back(rr);
+            }
+            r = q;
+        }
+        ps.c1 = P.chunks.size();
+        ps.scale = scale;
+        P.passes.push_back(ps);
+        P.tile_passes++;
+        return j;
+    }
+
+    void run_plain() {
+        for (size_t p = P.begin; p < end; ++p) emit_plain(p);
+    }
+
+    void run_fused() {
+        const bool tile_ok = P.n >= cfg.B + 1 && tile_supported(P.dtype, cfg.B, cfg.m);
+        size_t p = P.begin;
+        while (p < end) {
+            const size_t fs = span_len(p, cfg.span_m);
+            size_t ft = 0;
+            int gbest = 0;
+            if (tile_ok) {
+                for (int g = 0; g <= cfg.max_virtual && g <= P.n - cfg.B; ++g) {
+                    const size_t f = tile_len(p, g);
+                    if (f > ft) {
+                        ft = f;
+                        gbest = g;
+                    }
+                }
+            }
+            if (ft > fs && ft >= 2) {
+                p = emit_tile(p, gbest);
+            } else if (fs >= 2 || cfg.commuting) {
+                const size_t q = emit_span(p);
+                if (q - p == 1 && P.passes.back().kind == kSpan) {
+                    // a lone rotation: a plain sweep is the same traffic
+                    P.passes.pop_back();
+                    P.span_passes--;
+                    recs.pop_back();
+                    emit_plain(p);
+                }
+                p = q;
+            } else {
+                emit_plain(p);
+                ++p;
+            }
+        }
+    }
+};
+
+}  // namespace prx
+
+using namespace prx;
+
+// ---------------------------------------------------------------- plan API
+
+namespace prx {
+
+static void default_cfg(prx_dtype dt, PlanCfg &c) {
+    c.B = (dt == PRX_C64) ? 12 : 11;
+    c.m = 4;
+    c.span_m = 4;
+    c.max_fuse = 64;
+    c.max_virtual = 2;
+    c.renorm_every = (dt == PRX_C64) ? 1 : -1;
+    c.commuting = false;
+}
+
+// autotune cache: key "gfx950/<n>/<dtype>"
+static std::mutex g_tune_mu;
+static std::map<std::string, prx_plan_opts> g_tune;
+
+static std::string tune_key(int n, prx_dtype dt) {
+    return "gfx950/" + std::to_string(n) + "/" + (dt == PRX_C64 ? "c64" : "c128");
+}
+
+static void apply_opts(const prx_plan_opts *o, PlanCfg &c) {
+    if (!o) return;
+    if (o->tile_qubits) c.B = o->tile_qubits;
+    if (o->chunk_rank) c.m = o->chunk_rank;
+    if (o->span_max) c.span_m = o->span_max;
+    if (o->max_fuse) c.max_fuse = o->max_fuse;
+    if (o->max_virtual) c.max_virtual = o->max_virtual < 0 ? 0 : o->max_virtual;
+    if (o->renorm_every) c.renorm_every = o->renorm_every;
+    if (o->commuting) c.commuting = o->commuting > 0;
+}
+
+template <typename T>
+static void pack_records(prx_plan &P, const std::vector<RotRecD> &recs) {
+    P.rot_table.resize(recs.size() * sizeof(RotRec<T>));
+    RotRec<T> *out = reinterpret_cast<RotRec<T> *>(P.rot_table.data());
+    for (size_t i = 0; i < recs.size(); ++i) {
+        RotRec<T> r;
+        std::memset(&r, 0, sizeof(r));
+        r.z = recs[i].z;
+        r.zhigh = recs[i].zhigh;
+        r.info = recs[i].info;
+        r.tau = (T)recs[i].tau;
+        out[i] = r;
+    }
+}
+
+}  // namespace prx
+
+extern "C" {
+
+prx_status prx_plan_create(const prx_sched *sched, int n, prx_dtype dtype, size_t begin,
+                           size_t end, prx_kernel kernel, const prx_plan_opts *opts,
+                           prx_plan **out) {
+    if (!sched || !out) return fail(PRX_ERR_INVALID, "null pointer");
+    if (dtype != PRX_C64 && dtype != PRX_C128) return fail(PRX_ERR_INVALID, "bad dtype");
+    if (kernel < PRX_PLAIN || kernel > PRX_AUTO) return fail(PRX_ERR_INVALID, "bad kernel");
+    if (n != sched->n) return fail(PRX_ERR_INVALID, "n differs from the schedule's n");
+    if (n < 1) return fail(PRX_ERR_INVALID, "n must be >= 1");
+    if (n > 40) return fail(PRX_ERR_UNSUPPORTED, "n > 40 does not fit one device");
+    if (begin > end || end > sched->x.size()) return fail(PRX_ERR_INVALID, "bad rotation range");
+    prx_plan *P = new (std::nothrow) prx_plan;
+    if (!P) return fail(PRX_ERR_OOM, "out of host memory");
+    try {
+        P->n = n;
+        P->dtype = dtype;
+        P->kernel = kernel;
+        P->begin = 0;
+        default_cfg(dtype, P->cfg);
+        if (kernel == PRX_AUTO) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(tune_key(n, dtype));
+            if (it != g_tune.end()) apply_opts(&it->second, P->cfg);
+        }
+        apply_opts(opts, P->cfg);
+        const bool fused = kernel != PRX_PLAIN;
+        if (fused) {
+            if (!tile_supported(dtype, P->cfg.B, P->cfg.m) && P->n > P->cfg.B) {
+                delete P;
+                return fail(PRX_ERR_UNSUPPORTED, "tile shape (tile_qubits, chunk_rank) not built");
+            }
+            if (!span_supported(dtype, P->cfg.span_m) || P->cfg.max_virtual > kMaxVirtual ||
+                P->cfg.max_fuse < 1 || P->cfg.max_fuse > 4096) {
+                delete P;
+                return fail(PRX_ERR_INVALID, "bad planner option");
+            }
+        }
+        P->rots.reserve(end - begin);
+        for (size_t j = begin; j < end; ++j) {
+            KRot k{sched->x[j], sched->z[j], sched->phi[j], j};
+            if (fused && std::fabs(std::cos(k.phi)) < 0.5) {
+                k.phi = sched->phi[j] * 0.5;
+                P->rots.push_back(k);
+            }
+            P->rots.push_back(k);
+        }
+        P->end = P->rots.size();
+        Builder bld(*P, P->end);
+        // span passes need 2^(n - m) >= 1 cosets; tiny states fall back to plain
+        if (!fused || n < 4)
+            bld.run_plain();
+        else {
+            if (P->cfg.span_m > n - 1) P->cfg.span_m = std::max(1, n - 1);
+            bld.run_fused();
+        }
+        // renormalisation between consecutive fused passes
+        if (dtype == PRX_C64 && P->cfg.renorm_every > 0) {
+            int f = 0;
+            for (size_t i = 0; i + 1 < P->passes.size(); ++i) {
+                Pass &a = P->passes[i];
+                Pass &b = P->passes[i + 1];
+                if (a.kind == kPlain) continue;
+                ++f;
+                if (b.kind != kPlain && f % P->cfg.renorm_every == 0) {
+                    a.norm_out = true;
+                    b.renorm_in = true;
+                }
+            }
+        }
+        if (dtype == PRX_C64)
+            pack_records<float>(*P, bld.recs);
+        else
+            pack_records<double>(*P, bld.recs);
+        // workspace layout
+        size_t maxblocks = 1;
+        for (const Pass &ps : P->passes) {
+            if (!ps.norm_out) continue;
+            const size_t nb = ps.kind == kSpan ? span_blocks(n, ps.m) : tile_blocks(n, ps.B);
+            maxblocks = std::max(maxblocks, nb);
+        }
+        WsLayout &w = P->ws;
+        w.rot_off = 0;
+        w.rot_bytes = P->rot_table.size();
+        w.chunk_off = align256(w.rot_off + w.rot_bytes);
+        w.chunk_bytes = P->chunks.size() * sizeof(ChunkRec);
+        w.part_off = align256(w.chunk_off + w.chunk_bytes);
+        w.part_bytes = maxblocks * sizeof(double);
+        w.scal_off = align256(w.part_off + w.part_bytes);
+        w.scal_bytes = 64;
+        w.total = align256(w.scal_off + w.scal_bytes);
+    } catch (const std::bad_alloc &) {
+        delete P;
+        return fail(PRX_ERR_OOM, "out of host memory");
+    }
+    *out = P;
+    return PRX_OK;
+}
+
+prx_status prx_plan_get_info(const prx_plan *P, prx_plan_info *o) {
+    if (!P || !o) return fail(PRX_ERR_INVALID, "null pointer");
+    std::memset(o, 0, sizeof(*o));
+    size_t srcs = 0;
+    if (!P->rots.empty()) {
+        srcs = 1;
+        for (size_t i = 1; i < P->rots.size(); ++i) srcs += P->rots[i].src != P->rots[i - 1].src;
+    }
+    o->rotations = srcs;
+    o->kernel_rotations = P->rots.size();
+    o->passes = P->passes.size();
+    o->plain_passes = P->plain_passes;
+    o->span_passes = P->span_passes;
+    o->tile_passes = P->tile_passes;
+    o->workspace_bytes = P->ws.total;
+    o->mean_fuse = P->passes.empty() ? 0.0 : (double)P->rots.size() / (double)P->passes.size();
+    o->tile_qubits = P->cfg.B;
+    o->chunk_rank = P->cfg.m;
+    return PRX_OK;
+}
+
+void prx_plan_destroy(prx_plan *P) { delete P; }
+
+prx_status prx_plan_upload(const prx_plan *P, void *ws, size_t ws_bytes, void *stream) {
+    if (!P || !ws) return fail(PRX_ERR_INVALID, "null pointer");
+    if (ws_bytes < P->ws.total) return fail(PRX_ERR_INVALID, "workspace too small");
+    if ((uintptr_t)ws & 255) return fail(PRX_ERR_INVALID, "workspace not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    if (P->ws.rot_bytes)
+        PRX_HIP(hipMemcpyAsync(base + P->ws.rot_off, P->rot_table.data(), P->ws.rot_bytes,
+                               hipMemcpyHostToDevice, s));
+    if (P->ws.chunk_bytes)
+        PRX_HIP(hipMemcpyAsync(base + P->ws.chunk_off, P->chunks.data(), P->ws.chunk_bytes,
+                               hipMemcpyHostToDevice, s));
+    return PRX_OK;
+}
+
+prx_status prx_plan_execute(const prx_plan *P, void *psi, void *ws, size_t ws_bytes,
+                            void *stream) {
+    if (!P || !psi || !ws) return fail(PRX_ERR_INVALID, "null pointer");
+    if (ws_bytes < P->ws.total) return fail(PRX_ERR_INVALID, "workspace too small");
+    if (((uintptr_t)psi & 15) || ((uintptr_t)ws & 255))
+        return fail(PRX_ERR_INVALID, "misaligned state or workspace");
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    const void *rots = base + P->ws.rot_off;
+    const ChunkRec *chunks = (const ChunkRec *)(base + P->ws.chunk_off);
+    double *part = (double *)(base + P->ws.part_off);
+    double *scal = (double *)(base + P->ws.scal_off);
+    const size_t rsz = P->dtype == PRX_C64 ? sizeof(RotRec<float>) : sizeof(RotRec<double>);
+    (void)rsz;
+    for (const Pass &ps : P->passes) {
+        const double *rin = ps.renorm_in ? scal : nullptr;
+        double *nout = ps.norm_out ? part : nullptr;
+        unsigned blocks = 0;
+        hipError_t e = hipSuccess;
+        if (ps.kind == kPlain) {
+            e = launch_plain(P->dtype, psi, plain_args(P->n, P->rots[ps.r0]), s);
+        } else if (ps.kind == kSpan) {
+            SpanArgs a;
+            std::memset(&a, 0, sizeof(a));
+            for (int i = 0; i < ps.m; ++i) {
+                a.basis[i] = ps.basis[i];
+                a.pivot[i] = ps.pivot[i];
+            }
+            a.rot_begin = (uint32_t)ps.r0;
+            a.rot_count = (uint32_t)(ps.r1 - ps.r0);
+            a.n = P->n;
+            a.scale = ps.scale;
+            e = launch_span(P->dtype, ps.m, psi, a, rots, rin, nout, s, &blocks);
+        } else {
+            TileArgs a;
+            std::memset(&a, 0, sizeof(a));
+            for (int i = 0; i < (1 << ps.g); ++i) a.vcomb[i] = ps.vcomb[i];
+            for (int i = 0; i < ps.g; ++i) a.tpivot[i] = ps.tpivot[i];
+            a.n = P->n;
+            a.b = ps.b;
+            a.g = ps.g;
+            a.chunk_begin = (uint32_t)ps.c0;
+            a.chunk_count = (uint32_t)(ps.c1 - ps.c0);
+            a.scale = ps.scale;
+            e = launch_tile(P->dtype, ps.B, ps.m, psi, a, rots, chunks, rin, nout, s, &blocks);
+        }
+        if (e != hipSuccess) return hip_fail(e, "pass launch");
+        if (ps.norm_out) {
+            e = launch_renorm_finish(part, blocks, scal, s);
+            if (e != hipSuccess) return hip_fail(e, "renorm launch");
+        }
+    }
+    return PRX_OK;
+}
+
+prx_status prx_plan_pass(const prx_plan *P, size_t i, prx_pass_info *o) {
+    if (!P || !o) return fail(PRX_ERR_INVALID, "null pointer");
+    if (i >= P->passes.size()) return fail(PRX_ERR_INVALID, "pass index out of range");
+    const Pass &ps = P->passes[i];
+    std::memset(o, 0, sizeof(*o));
+    o->kind = ps.kind;
+    o->rot_begin = ps.r0;
+    o->rot_count = ps.r1 - ps.r0;
+    o->chunk_begin = ps.c0;
+    o->chunk_count = ps.c1 - ps.c0;
+    o->B = ps.B;
+    o->b = ps.b;
+    o->g = ps.g;
+    o->m = ps.m;
+    for (int k = 0; k < kMaxChunkRank; ++k) {
+        o->basis[k] = ps.basis[k];
+        o->pivot[k] = ps.pivot[k];
+    }
+    for (int k = 0; k < (1 << kMaxVirtual); ++k) o->vcomb[k] = ps.vcomb[k];
+    for (int k = 0; k < kMaxVirtual; ++k) o->tpivot[k] = ps.tpivot[k];
+    o->scale = ps.scale;
+    o->norm_out = ps.norm_out;
+    o->renorm_in = ps.renorm_in;
+    return PRX_OK;
+}
+
+prx_status prx_plan_chunk(const prx_plan *P, size_t i, prx_chunk_info *o) {
+    if (!P || !o) return fail(PRX_ERR_INVALID, "null pointer");
+    if (i >= P->chunks.size()) return fail(PRX_ERR_INVALID, "chunk index out of range");
+    const ChunkRec &c = P->chunks[i];
+    std::memset(o, 0, sizeof(*o));
+    for (int k = 0; k < kMaxChunkRank; ++k) {
+        o->basis[k] = c.basis[k];
+        o->pivot[k] = c.pivot[k];
+    }
+    o->rot_begin = c.rot_begin;
+    o->rot_count = c.rot_count;
+    return PRX_OK;
+}
+
+prx_status prx_plan_rotation(const prx_plan *P, size_t i, prx_rot_info *o) {
+    if (!P || !o) return fail(PRX_ERR_INVALID, "null pointer");
+    if (i >= P->rots.size()) return fail(PRX_ERR_INVALID, "rotation index out of range");
+    const KRot &k = P->rots[i];
+    std::memset(o, 0, sizeof(*o));
+    o->x = k.x;
+    o->z = k.z;
+    o->phi = k.phi;
+    o->source = k.src;
+    if (P->dtype == PRX_C64) {
+        const RotRec<float> &r = reinterpret_cast<const RotRec<float> *>(P->rot_table.data())[i];
+        o->zframe = r.z;
+        o->zhigh = r.zhigh;
+        o->slot = r.info & 15u;
+        o->imag = (r.info >> 4) & 1u;
+        o->zeta = (r.info >> 8) & 0xffu;
+        o->tau = r.tau;
+    } else {
+        const RotRec<double> &r = reinterpret_cast<const RotRec<double> *>(P->rot_table.data())[i];
+        o->zframe = r.z;
+        o->zhigh = r.zhigh;
+        o->slot = r.info & 15u;
+        o->imag = (r.info >> 4) & 1u;
+        o->zeta = (r.info >> 8) & 0xffu;
+        o->tau = r.tau;
+    }
+    return PRX_OK;
+}
+
+size_t prx_workspace_bytes(int n, prx_dtype dtype, const prx_sched *sched, prx_kernel kernel) {
+    if (!sched) return 0;
+    prx_plan *P = nullptr;
+    if (prx_plan_create(sched, n, dtype, 0, sched->x.size(), kernel, nullptr, &P) != PRX_OK)
+        return 0;
+    const size_t b = P->ws.total;
+    prx_plan_destroy(P);
+    return b;
+}
+
+prx_status prx_apply_range(void *psi, int n, prx_dtype dtype, const prx_sched *sched,
+                           size_t begin, size_t end, prx_kernel kernel, void *ws,
+                           size_t ws_bytes, void *stream) {
+    prx_plan *P = nullptr;
+    prx_status st = prx_plan_create(sched, n, dtype, begin, end, kernel, nullptr, &P);
+    if (st != PRX_OK) return st;
+    st = prx_plan_upload(P, ws, ws_bytes, stream);
+    if (st == PRX_OK) st = prx_plan_execute(P, psi, ws, ws_bytes, stream);
+    if (st == PRX_OK) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    prx_plan_destroy(P);
+    return st;
+}
+
+// ------------------------------------------------------------ reductions
+
+size_t prx_reduce_workspace_bytes(int n) {
+    (void)n;
+    return align256((2 * kReduceBlocks + 8) * sizeof(double));
+}
+
+static prx_status check_state(const void *p, int n, prx_dtype dt) {
+    if (!p) return fail(PRX_ERR_INVALID, "null state");
+    if (n < 1 || n > 40) return fail(PRX_ERR_INVALID, "n must be in [1, 40]");
+    if (dt != PRX_C64 && dt != PRX_C128) return fail(PRX_ERR_INVALID, "bad dtype");
+    if ((uintptr_t)p & 15) return fail(PRX_ERR_INVALID, "state not 16-byte aligned");
+    return PRX_OK;
+}
+
+prx_status prx_overlap(const void *psi0, const void *psi, int n, prx_dtype dtype,
+                       double out_re_im[2], void *ws, size_t ws_bytes, void *stream) {
+    prx_status st = check_state(psi0, n, dtype);
+    if (st == PRX_OK) st = check_state(psi, n, dtype);
+    if (st != PRX_OK) return st;
+    if (!out_re_im || !ws) return fail(PRX_ERR_INVALID, "null pointer");
+    if (ws_bytes < prx_reduce_workspace_bytes(n)) return fail(PRX_ERR_INVALID, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    double *w = (double *)ws;
+    hipError_t e = launch_overlap(dtype, psi0, psi, n, w, s);
+    if (e != hipSuccess) return hip_fail(e, "overlap launch");
+    double h[2];
+    PRX_HIP(hipMemcpyAsync(h, w + 2 * kReduceBlocks, sizeof(h), hipMemcpyDeviceToHost, s));
+    PRX_HIP(hipStreamSynchronize(s));
+    out_re_im[0] = h[0];
+    out_re_im[1] = h[1];
+    return PRX_OK;
+}
+
+prx_status prx_norm2(const void *psi, int n, prx_dtype dtype, double *out, void *ws,
+                     size_t ws_bytes, void *stream) {
+    prx_status st = check_state(psi, n, dtype);
+    if (st != PRX_OK) return st;
+    if (!out || !ws) return fail(PRX_ERR_INVALID, "null pointer");
+    if (ws_bytes < prx_reduce_workspace_bytes(n)) return fail(PRX_ERR_INVALID, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    double *w = (double *)ws;
+    hipError_t e = launch_norm2(dtype, psi, n, w, s);
+    if (e != hipSuccess) return hip_fail(e, "norm launch");
+    double h[2];
+    PRX_HIP(hipMemcpyAsync(h, w + 2 * kReduceBlocks, sizeof(h), hipMemcpyDeviceToHost, s));
+    PRX_HIP(hipStreamSynchronize(s));
+    *out = h[0];
+    return PRX_OK;
+}
+
+prx_status prx_amplitude(const void *psi, int n, prx_dtype dtype, uint64_t k,
+                         double out_re_im[2], void *stream) {
+    prx_status st = check_state(psi, n, dtype);
+    if (st != PRX_OK) return st;
+    if (!out_re_im) return fail(PRX_ERR_INVALID, "null pointer");
+    if (k >> n) return fail(PRX_ERR_INVALID, "index out of range");
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == PRX_C64) {
+        float h[2];
+        PRX_HIP(hipMemcpyAsync(h, (const char *)psi + k * 8, 8, hipMemcpyDeviceToHost, s));
+        PRX_HIP(hipStreamSynchronize(s));
+        out_re_im[0] = h[0];
+        out_re_im[1] = h[1];
+    } else {
+        double h[2];
+        PRX_HIP(hipMemcpyAsync(h, (const char *)psi + k * 16, 16, hipMemcpyDeviceToHost, s));
+        PRX_HIP(hipStreamSynchronize(s));
+        out_re_im[0] = h[0];
+        out_re_im[1] = h[1];
+    }
+    return PRX_OK;
+}
+
+prx_status prx_renormalize(void *psi, int n, prx_dtype dtype, void *ws, size_t ws_bytes,
+                           void *stream) {
+    double nrm = 0.0;
+    prx_status st = prx_norm2(psi, n, dtype, &nrm, ws, ws_bytes, stream);
+    if (st != PRX_OK) return st;
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return fail(PRX_ERR_INVALID, "state has zero or non-finite norm");
+    hipStream_t s = (hipStream_t)stream;
+    double *w = (double *)ws;
+    const double scale = 1.0 / std::sqrt(nrm);
+    PRX_HIP(hipMemcpyAsync(w + 2 * kReduceBlocks + 4, &scale, sizeof(double),
+                           hipMemcpyHostToDevice, s));
+    hipError_t e = launch_scale(dtype, psi, n, w + 2 * kReduceBlocks + 4, s);
+    if (e != hipSuccess) return hip_fail(e, "scale launch");
+    PRX_HIP(hipStreamSynchronize(s));
+    return PRX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,457 @@
+"""ctypes binding of ``libprx.so`` with the C ABI's names (include/prx.h).
+
+Argument marshalling only: every computation runs in the library.  Device
+buffers may be given as torch tensors (their ``data_ptr()`` is passed) or
+as integer addresses; streams as ``torch.cuda.Stream`` objects, raw
+integers, or None (the default stream).  A non-OK status raises
+``PrxError`` carrying the library's message.
+
+The library must have been built (``python -m paper_2504_17881_amd.build``);
+importing this module without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libprx.so")
+
+PRX_OK, PRX_ERR_INVALID, PRX_ERR_OOM, PRX_ERR_HIP, PRX_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+PRX_C64, PRX_C128 = 1, 2
+PRX_PLAIN, PRX_FUSED, PRX_AUTO = 0, 1, 2
+PRX_REORDER_NONE, PRX_REORDER_COMMUTING, PRX_REORDER_SUFFIX = 0, 1, 2
+
+_STATUS = {0: "PRX_OK", 1: "PRX_ERR_INVALID", 2: "PRX_ERR_OOM", 3: "PRX_ERR_HIP",
+           4: "PRX_ERR_UNSUPPORTED"}
+
+
+class PrxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_2504_17881_amd.build` (no CPU fallback exists)")
+
+# PyTorch ships its own HIP runtime (same soname).  Load it first so that
+# libprx.so binds to that one runtime: device pointers and streams from torch
+# are then valid in the library.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the C ABI also works without torch (raw addresses)
+    torch = None
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+
+
+class prx_plan_opts(ctypes.Structure):
+    _fields_ = [("tile_qubits", ctypes.c_int), ("chunk_rank", ctypes.c_int),
+                ("max_fuse", ctypes.c_int), ("span_max", ctypes.c_int),
+                ("max_virtual", ctypes.c_int), ("renorm_every", ctypes.c_int),
+                ("commuting", ctypes.c_int)]
+
+
+class prx_plan_info(ctypes.Structure):
+    _fields_ = [("rotations", _sz), ("kernel_rotations", _sz), ("passes", _sz),
+                ("plain_passes", _sz), ("span_passes", _sz), ("tile_passes", _sz),
+                ("workspace_bytes", _sz), ("mean_fuse", ctypes.c_double),
+                ("tile_qubits", ctypes.c_int), ("chunk_rank", ctypes.c_int)]
+
+
+class prx_pass_info(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("rot_begin", _sz), ("rot_count", _sz),
+                ("chunk_begin", _sz), ("chunk_count", _sz),
+                ("B", ctypes.c_int), ("b", ctypes.c_int), ("g", ctypes.c_int),
+                ("m", ctypes.c_int),
+                ("basis", ctypes.c_uint64 * 6), ("pivot", ctypes.c_uint32 * 6),
+                ("vcomb", ctypes.c_uint64 * 8), ("tpivot", ctypes.c_uint32 * 3),
+                ("scale", ctypes.c_double), ("norm_out", ctypes.c_int),
+                ("renorm_in", ctypes.c_int)]
+
+
+class prx_chunk_info(ctypes.Structure):
+    _fields_ = [("basis", ctypes.c_uint32 * 6), ("pivot", ctypes.c_uint32 * 6),
+                ("rot_begin", _sz), ("rot_count", _sz)]
+
+
+class prx_rot_info(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_uint64), ("z", ctypes.c_uint64), ("phi", ctypes.c_double),
+                ("source", _sz), ("zframe", ctypes.c_uint64), ("zhigh", ctypes.c_uint64),
+                ("slot", ctypes.c_uint32), ("imag", ctypes.c_uint32),
+                ("zeta", ctypes.c_uint32), ("tau", ctypes.c_double)]
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_i = ctypes.c_int
+_st = ctypes.c_int
+_sig("prx_last_error", ctypes.c_char_p)
+_sig("prx_version", ctypes.c_char_p)
+_sig("prx_ham_create", _st, _i, _sz, _u64p, _u64p, _dp, ctypes.POINTER(_vp))
+_sig("prx_ham_destroy", None, _vp)
+_sig("prx_ham_lambda", _st, _vp, _dp)
+_sig("prx_sched_trotter", _st, _vp, _i, ctypes.c_double, _i, _i, ctypes.POINTER(_vp))
+_sig("prx_sched_qdrift", _st, _vp, ctypes.c_double, _sz, ctypes.c_uint64, ctypes.POINTER(_vp))
+_sig("prx_sched_partial", _st, _vp, _sz, ctypes.c_double, _i, _sz, ctypes.c_uint64, _i,
+     ctypes.POINTER(_vp))
+_sig("prx_sched_from_rotations", _st, _i, _sz, _u64p, _u64p, _dp, ctypes.POINTER(_vp))
+_sig("prx_sched_view", _st, _vp, ctypes.POINTER(_i), ctypes.POINTER(_sz),
+     ctypes.POINTER(_u64p), ctypes.POINTER(_u64p), ctypes.POINTER(_dp))
+_sig("prx_sched_destroy", None, _vp)
+_sig("prx_plan_create", _st, _vp, _i, _i, _sz, _sz, _i, ctypes.POINTER(prx_plan_opts),
+     ctypes.POINTER(_vp))
+_sig("prx_plan_get_info", _st, _vp, ctypes.POINTER(prx_plan_info))
+_sig("prx_plan_destroy", None, _vp)
+_sig("prx_plan_upload", _st, _vp, _vp, _sz, _vp)
+_sig("prx_plan_execute", _st, _vp, _vp, _vp, _sz, _vp)
+_sig("prx_plan_pass", _st, _vp, _sz, ctypes.POINTER(prx_pass_info))
+_sig("prx_plan_chunk", _st, _vp, _sz, ctypes.POINTER(prx_chunk_info))
+_sig("prx_plan_rotation", _st, _vp, _sz, ctypes.POINTER(prx_rot_info))
+_sig("prx_workspace_bytes", _sz, _i, _i, _vp, _i)
+_sig("prx_apply_range", _st, _vp, _i, _i, _vp, _sz, _sz, _i, _vp, _sz, _vp)
+_sig("prx_reduce_workspace_bytes", _sz, _i)
+_sig("prx_overlap", _st, _vp, _vp, _i, _i, _dp, _vp, _sz, _vp)
+_sig("prx_amplitude", _st, _vp, _i, _i, ctypes.c_uint64, _dp, _vp)
+_sig("prx_norm2", _st, _vp, _i, _i, _dp, _vp, _sz, _vp)
+_sig("prx_renormalize", _st, _vp, _i, _i, _vp, _sz, _vp)
+_sig("prx_batch_create", _st, _sz, ctypes.POINTER(_i), ctypes.POINTER(_vp), _i, _u64p,
+     ctypes.POINTER(_vp))
+_sig("prx_batch_workspace_bytes", _sz, _vp)
+_sig("prx_batch_upload", _st, _vp, _vp, _sz, _vp)
+_sig("prx_batch_execute", _st, _vp, ctypes.POINTER(_vp), _vp, _sz, _vp, _vp)
+_sig("prx_batch_destroy", None, _vp)
+_sig("prx_batch_run", _st, _sz, ctypes.POINTER(_vp), ctypes.POINTER(_i), ctypes.POINTER(_vp),
+     _i, _u64p, _dp, _vp, _sz, _vp)
+_sig("prx_autotune", _st, _vp, _i, _i, _vp, _vp, _sz, _vp, ctypes.POINTER(prx_plan_opts),
+     ctypes.POINTER(_i))
+_sig("prx_autotune_save", _st, ctypes.c_char_p)
+_sig("prx_autotune_load", _st, ctypes.c_char_p)
+_sig("prx_autotune_lookup", _st, _i, _i, ctypes.POINTER(prx_plan_opts))
+
+EXPORTED = sorted(n for n in dir(_lib) if n.startswith("prx_"))
+
+
+def _check(st: int):
+    if st != PRX_OK:
+        raise PrxError(st, _lib.prx_last_error().decode(errors="replace"))
+
+
+def _ptr(buf) -> int | None:
+    """Device or host address of a torch tensor / numpy array / int."""
+    if buf is None:
+        return None
+    if isinstance(buf, int):
+        return buf
+    if hasattr(buf, "data_ptr"):
+        return buf.data_ptr()
+    if isinstance(buf, np.ndarray):
+        return buf.ctypes.data
+    raise TypeError(f"cannot take the address of {type(buf)!r}")
+
+
+def _nbytes(buf, given=None) -> int:
+    if given is not None:
+        return int(given)
+    if hasattr(buf, "numel") and hasattr(buf, "element_size"):
+        return buf.numel() * buf.element_size()
+    if isinstance(buf, np.ndarray):
+        return buf.nbytes
+    raise TypeError("pass the buffer size explicitly")
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # torch.cuda.Stream
+
+
+def _u64(a):
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return a, a.ctypes.data_as(_u64p)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+# ------------------------------------------------------------------ errors
+
+def prx_last_error() -> str:
+    return _lib.prx_last_error().decode(errors="replace")
+
+
+def prx_version() -> str:
+    return _lib.prx_version().decode()
+
+
+# ------------------------------------------------------------- Hamiltonian
+
+def prx_ham_create(n: int, x, z, h) -> int:
+    xa, xp = _u64(x)
+    za, zp = _u64(z)
+    ha, hp = _f64(h)
+    if not (len(xa) == len(za) == len(ha)):
+        raise ValueError("x, z, h lengths differ")
+    out = _vp()
+    _check(_lib.prx_ham_create(int(n), len(xa), xp, zp, hp, ctypes.byref(out)))
+    return out.value
+
+
+def prx_ham_destroy(ham: int) -> None:
+    _lib.prx_ham_destroy(ham)
+
+
+def prx_ham_lambda(ham: int) -> float:
+    v = ctypes.c_double()
+    _check(_lib.prx_ham_lambda(ham, ctypes.byref(v)))
+    return v.value
+
+
+# --------------------------------------------------------------- schedules
+
+def prx_sched_trotter(ham: int, order: int, t: float, steps: int,
+                      reorder: int = PRX_REORDER_NONE) -> int:
+    out = _vp()
+    _check(_lib.prx_sched_trotter(ham, order, t, steps, reorder, ctypes.byref(out)))
+    return out.value
+
+
+def prx_sched_qdrift(ham: int, t: float, N: int, seed: int) -> int:
+    out = _vp()
+    _check(_lib.prx_sched_qdrift(ham, t, N, seed, ctypes.byref(out)))
+    return out.value
+
+
+def prx_sched_partial(ham: int, L_det: int, t: float, steps: int, r_per_step: int,
+                      seed: int, reorder: int = PRX_REORDER_NONE) -> int:
+    out = _vp()
+    _check(_lib.prx_sched_partial(ham, L_det, t, steps, r_per_step, seed, reorder,
+                                  ctypes.byref(out)))
+    return out.value
+
+
+def prx_sched_from_rotations(n: int, x, z, phi) -> int:
+    xa, xp = _u64(x)
+    za, zp = _u64(z)
+    pa, pp = _f64(phi)
+    out = _vp()
+    _check(_lib.prx_sched_from_rotations(int(n), len(xa), xp, zp, pp, ctypes.byref(out)))
+    return out.value
+
+
+def prx_sched_view(sched: int):
+    """(n, x, z, phi) copied into numpy arrays."""
+    n = ctypes.c_int()
+    M = ctypes.c_size_t()
+    xp, zp, pp = _u64p(), _u64p(), _dp()
+    _check(_lib.prx_sched_view(sched, ctypes.byref(n), ctypes.byref(M), ctypes.byref(xp),
+                               ctypes.byref(zp), ctypes.byref(pp)))
+    m = M.value
+    if m == 0:
+        return n.value, np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0)
+    x = np.ctypeslib.as_array(xp, shape=(m,)).copy()
+    z = np.ctypeslib.as_array(zp, shape=(m,)).copy()
+    p = np.ctypeslib.as_array(pp, shape=(m,)).copy()
+    return n.value, x, z, p
+
+
+def prx_sched_destroy(sched: int) -> None:
+    _lib.prx_sched_destroy(sched)
+
+
+# -------------------------------------------------------------------- plans
+
+def _opts(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, prx_plan_opts):
+        return ctypes.byref(opts)
+    o = prx_plan_opts()
+    for k, v in dict(opts).items():
+        setattr(o, k, int(v))
+    return ctypes.byref(o)
+
+
+def prx_plan_create(sched: int, n: int, dtype: int, begin: int, end: int, kernel: int,
+                    opts=None) -> int:
+    out = _vp()
+    _check(_lib.prx_plan_create(sched, n, dtype, begin, end, kernel, _opts(opts),
+                                ctypes.byref(out)))
+    return out.value
+
+
+def prx_plan_get_info(plan: int) -> dict:
+    i = prx_plan_info()
+    _check(_lib.prx_plan_get_info(plan, ctypes.byref(i)))
+    return {f: getattr(i, f) for f, _ in prx_plan_info._fields_}
+
+
+def prx_plan_destroy(plan: int) -> None:
+    _lib.prx_plan_destroy(plan)
+
+
+def prx_plan_upload(plan: int, ws, stream=None, ws_bytes=None) -> None:
+    _check(_lib.prx_plan_upload(plan, _ptr(ws), _nbytes(ws, ws_bytes), _stream(stream)))
+
+
+def prx_plan_execute(plan: int, psi, ws, stream=None, ws_bytes=None) -> None:
+    _check(_lib.prx_plan_execute(plan, _ptr(psi), _ptr(ws), _nbytes(ws, ws_bytes),
+                                 _stream(stream)))
+
+
+def prx_plan_pass(plan: int, i: int) -> dict:
+    o = prx_pass_info()
+    _check(_lib.prx_plan_pass(plan, i, ctypes.byref(o)))
+    d = {f: getattr(o, f) for f, _ in prx_pass_info._fields_}
+    for k in ("basis", "pivot", "vcomb", "tpivot"):
+        d[k] = list(d[k])
+    return d
+
+
+def prx_plan_chunk(plan: int, i: int) -> dict:
+    o = prx_chunk_info()
+    _check(_lib.prx_plan_chunk(plan, i, ctypes.byref(o)))
+    d = {f: getattr(o, f) for f, _ in prx_chunk_info._fields_}
+    d["basis"] = list(d["basis"])
+    d["pivot"] = list(d["pivot"])
+    return d
+
+
+def prx_plan_rotation(plan: int, i: int) -> dict:
+    o = prx_rot_info()
+    _check(_lib.prx_plan_rotation(plan, i, ctypes.byref(o)))
+    return {f: getattr(o, f) for f, _ in prx_rot_info._fields_}
+
+
+# ------------------------------------------------------------ apply/reduce
+
+def prx_workspace_bytes(n: int, dtype: int, sched: int, kernel: int) -> int:
+    return int(_lib.prx_workspace_bytes(n, dtype, sched, kernel))
+
+
+def prx_apply_range(psi, n: int, dtype: int, sched: int, begin: int, end: int, kernel: int,
+                    ws, stream=None, ws_bytes=None) -> None:
+    _check(_lib.prx_apply_range(_ptr(psi), n, dtype, sched, begin, end, kernel, _ptr(ws),
+                                _nbytes(ws, ws_bytes), _stream(stream)))
+
+
+def prx_reduce_workspace_bytes(n: int) -> int:
+    return int(_lib.prx_reduce_workspace_bytes(n))
+
+
+def prx_overlap(psi0, psi, n: int, dtype: int, ws, stream=None, ws_bytes=None) -> complex:
+    out = (ctypes.c_double * 2)()
+    _check(_lib.prx_overlap(_ptr(psi0), _ptr(psi), n, dtype, out, _ptr(ws),
+                            _nbytes(ws, ws_bytes), _stream(stream)))
+    return complex(out[0], out[1])
+
+
+def prx_amplitude(psi, n: int, dtype: int, k: int, stream=None) -> complex:
+    out = (ctypes.c_double * 2)()
+    _check(_lib.prx_amplitude(_ptr(psi), n, dtype, k, out, _stream(stream)))
+    return complex(out[0], out[1])
+
+
+def prx_norm2(psi, n: int, dtype: int, ws, stream=None, ws_bytes=None) -> float:
+    v = ctypes.c_double()
+    _check(_lib.prx_norm2(_ptr(psi), n, dtype, ctypes.byref(v), _ptr(ws),
+                          _nbytes(ws, ws_bytes), _stream(stream)))
+    return v.value
+
+
+def prx_renormalize(psi, n: int, dtype: int, ws, stream=None, ws_bytes=None) -> None:
+    _check(_lib.prx_renormalize(_ptr(psi), n, dtype, _ptr(ws), _nbytes(ws, ws_bytes),
+                                _stream(stream)))
+
+
+# ------------------------------------------------------------------ batches
+
+def _ptr_array(items):
+    arr = (_vp * len(items))(*[_ptr(p) for p in items])
+    return arr
+
+
+def prx_batch_create(n_list, scheds, dtype: int, basis_idx) -> int:
+    S = len(n_list)
+    na = (ctypes.c_int * S)(*[int(v) for v in n_list])
+    sa = (_vp * S)(*scheds)
+    ba, bp = _u64(basis_idx)
+    out = _vp()
+    _check(_lib.prx_batch_create(S, na, sa, dtype, bp, ctypes.byref(out)))
+    return out.value
+
+
+def prx_batch_workspace_bytes(batch: int) -> int:
+    return int(_lib.prx_batch_workspace_bytes(batch))
+
+
+def prx_batch_upload(batch: int, ws, stream=None, ws_bytes=None) -> None:
+    _check(_lib.prx_batch_upload(batch, _ptr(ws), _nbytes(ws, ws_bytes), _stream(stream)))
+
+
+def prx_batch_execute(batch: int, psis, ws, overlaps_dev, stream=None, ws_bytes=None) -> None:
+    pa = _ptr_array(psis)
+    _check(_lib.prx_batch_execute(batch, pa, _ptr(ws), _nbytes(ws, ws_bytes),
+                                  _ptr(overlaps_dev), _stream(stream)))
+
+
+def prx_batch_destroy(batch: int) -> None:
+    _lib.prx_batch_destroy(batch)
+
+
+def prx_batch_run(psis, n_list, scheds, dtype: int, basis_idx, ws, stream=None,
+                  ws_bytes=None) -> np.ndarray:
+    S = len(psis)
+    pa = _ptr_array(psis)
+    na = (ctypes.c_int * S)(*[int(v) for v in n_list])
+    sa = (_vp * S)(*scheds)
+    ba, bp = _u64(basis_idx)
+    out = np.zeros(2 * S, dtype=np.float64)
+    _check(_lib.prx_batch_run(S, pa, na, sa, dtype, bp, out.ctypes.data_as(_dp), _ptr(ws),
+                              _nbytes(ws, ws_bytes), _stream(stream)))
+    return out[0::2] + 1j * out[1::2]
+
+
+# ---------------------------------------------------------------- autotune
+
+def prx_autotune(psi, n: int, dtype: int, sched: int, ws, stream=None, ws_bytes=None):
+    best = prx_plan_opts()
+    trials = ctypes.c_int()
+    _check(_lib.prx_autotune(_ptr(psi), n, dtype, sched, _ptr(ws), _nbytes(ws, ws_bytes),
+                             _stream(stream), ctypes.byref(best), ctypes.byref(trials)))
+    return {f: getattr(best, f) for f, _ in prx_plan_opts._fields_}, trials.value
+
+
+def prx_autotune_save(path: str) -> None:
+    _check(_lib.prx_autotune_save(path.encode()))
+
+
+def prx_autotune_load(path: str) -> None:
+    _check(_lib.prx_autotune_load(path.encode()))
+
+
+def prx_autotune_lookup(n: int, dtype: int):
+    o = prx_plan_opts()
+    st = _lib.prx_autotune_lookup(n, dtype, ctypes.byref(o))
+    if st == PRX_ERR_UNSUPPORTED:
+        return None
+    _check(st)
+    return {f: getattr(o, f) for f, _ in prx_plan_opts._fields_}

@@ -1,0 +1,164 @@
+"""Host-side checks of the C ABI (no device calls): exported symbols, input
+validation, schedules against the oracle's re-expansion, plan structure."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import schedules as S
+from paper_2504_17881_amd import prx as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "prx.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(prx_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_function_is_exported():
+    names = _declared()
+    assert len(names) >= 35
+    missing = [nm for nm in names if nm not in P.EXPORTED and not hasattr(P._lib, nm)]
+    assert not missing, missing
+
+
+def test_binding_names_match_abi():
+    for nm in _declared():
+        assert hasattr(P, nm), nm
+
+
+def test_version_and_error_string():
+    assert "gfx950" in P.prx_version()
+    with pytest.raises(P.PrxError) as e:
+        P.prx_ham_create(0, [1], [0], [1.0])
+    assert e.value.status == P.PRX_ERR_INVALID
+    assert "n must be" in P.prx_last_error()
+
+
+@pytest.mark.parametrize("args,frag", [
+    ((4, [1 << 4], [0], [1.0]), "beyond"),
+    ((4, [1], [1 << 5], [1.0]), "beyond"),
+    ((4, [1], [0], [float("nan")]), "non-finite"),
+    ((64, [1], [0], [1.0]), "n must be"),
+    ((4, [], [], []), "L must be"),
+])
+def test_ham_create_rejects(args, frag):
+    with pytest.raises(P.PrxError) as e:
+        P.prx_ham_create(*args)
+    assert e.value.status == P.PRX_ERR_INVALID and frag in str(e.value)
+
+
+def test_schedule_argument_checks():
+    H = P.prx_ham_create(3, [1, 2], [0, 2], [0.5, -0.2])
+    for bad in [lambda: P.prx_sched_trotter(H, 3, 1.0, 2),
+                lambda: P.prx_sched_trotter(H, 1, 1.0, 0),
+                lambda: P.prx_sched_trotter(H, 1, float("inf"), 2),
+                lambda: P.prx_sched_qdrift(H, 1.0, 0, 1),
+                lambda: P.prx_sched_partial(H, 3, 1.0, 1, 4, 1),
+                lambda: P.prx_sched_partial(H, 1, 1.0, 1, 0, 1)]:
+        with pytest.raises(P.PrxError) as e:
+            bad()
+        assert e.value.status == P.PRX_ERR_INVALID
+    Z = P.prx_ham_create(3, [1], [0], [0.0])
+    with pytest.raises(P.PrxError):
+        P.prx_sched_qdrift(Z, 1.0, 4, 1)
+    P.prx_ham_destroy(H)
+    P.prx_ham_destroy(Z)
+
+
+def test_lambda_matches_oracle():
+    x, z, h = synth.jw_hamiltonian(10, 120, 5)
+    H = P.prx_ham_create(10, x, z, h)
+    assert P.prx_ham_lambda(H) == S.lambda_of(h)
+    P.prx_ham_destroy(H)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("suffix", [False, True])
+def test_trotter_schedule_equals_oracle(order, suffix):
+    x, z, h = synth.jw_hamiltonian(12, 150, 6)
+    H = P.prx_ham_create(12, x, z, h)
+    s = P.prx_sched_trotter(H, order, 0.8, 3,
+                            P.PRX_REORDER_SUFFIX if suffix else P.PRX_REORDER_NONE)
+    n, rx, rz, rp = P.prx_sched_view(s)
+    ox, oz, op = S.trotter(x, z, h, order, 0.8, 3, suffix=suffix)
+    assert n == 12 and np.array_equal(rx, ox) and np.array_equal(rz, oz)
+    assert np.array_equal(rp, op)
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
+
+
+def test_qdrift_schedule_equals_oracle():
+    x, z, h = synth.jw_hamiltonian(16, 500, 1016)
+    H = P.prx_ham_create(16, x, z, h)
+    for seed in (0, 1, 255):
+        s = P.prx_sched_qdrift(H, 1.0, 2000, seed)
+        _, rx, rz, rp = P.prx_sched_view(s)
+        ox, oz, op = S.qdrift(x, z, h, 1.0, 2000, seed)
+        assert np.array_equal(rx, ox) and np.array_equal(rz, oz) and np.array_equal(rp, op)
+        P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
+
+
+@pytest.mark.parametrize("suffix", [False, True])
+def test_partial_schedule_equals_oracle(suffix):
+    x, z, h = synth.jw_hamiltonian(14, 400, 3)
+    H = P.prx_ham_create(14, x, z, h)
+    s = P.prx_sched_partial(H, 40, 1.0, 3, 70, 9,
+                            P.PRX_REORDER_SUFFIX if suffix else P.PRX_REORDER_NONE)
+    _, rx, rz, rp = P.prx_sched_view(s)
+    ox, oz, op = S.partial(x, z, h, 40, 1.0, 3, 70, 9, suffix=suffix)
+    assert len(rx) == 3 * (80 + 70)
+    assert np.array_equal(rx, ox) and np.array_equal(rz, oz) and np.array_equal(rp, op)
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
+
+
+def test_from_rotations_roundtrip_and_checks():
+    x, z, phi = synth.random_pauli_rotations(9, 50, 3)
+    s = P.prx_sched_from_rotations(9, x, z, phi)
+    n, rx, rz, rp = P.prx_sched_view(s)
+    assert n == 9 and np.array_equal(rx, x) and np.array_equal(rz, z) and np.array_equal(rp, phi)
+    P.prx_sched_destroy(s)
+    with pytest.raises(P.PrxError):
+        P.prx_sched_from_rotations(3, [8], [0], [0.1])
+    with pytest.raises(P.PrxError):
+        P.prx_sched_from_rotations(3, [1], [0], [float("nan")])
+
+
+def test_plan_range_and_option_checks():
+    x, z, phi = synth.random_pauli_rotations(10, 20, 3)
+    s = P.prx_sched_from_rotations(10, x, z, phi)
+    with pytest.raises(P.PrxError):
+        P.prx_plan_create(s, 10, P.PRX_C64, 5, 4, P.PRX_FUSED)
+    with pytest.raises(P.PrxError):
+        P.prx_plan_create(s, 10, P.PRX_C64, 0, 21, P.PRX_FUSED)
+    with pytest.raises(P.PrxError):
+        P.prx_plan_create(s, 11, P.PRX_C64, 0, 20, P.PRX_FUSED)
+    with pytest.raises(P.PrxError) as e:
+        P.prx_plan_create(s, 10, P.PRX_C64, 0, 20, P.PRX_FUSED, dict(tile_qubits=9, chunk_rank=2))
+    assert e.value.status == P.PRX_ERR_UNSUPPORTED
+    pl = P.prx_plan_create(s, 10, P.PRX_C64, 3, 3, P.PRX_FUSED)
+    assert P.prx_plan_get_info(pl)["passes"] == 0
+    P.prx_plan_destroy(pl)
+    # a workspace that is too small is rejected before any device call
+    pl = P.prx_plan_create(s, 10, P.PRX_C128, 0, 20, P.PRX_FUSED)
+    with pytest.raises(P.PrxError) as e:
+        P.prx_plan_upload(pl, 256, ws_bytes=16)
+    assert e.value.status == P.PRX_ERR_INVALID
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+
+
+def test_plain_plan_is_one_pass_per_rotation():
+    x, z, phi = synth.random_pauli_rotations(8, 30, 4)
+    s = P.prx_sched_from_rotations(8, x, z, phi)
+    pl = P.prx_plan_create(s, 8, P.PRX_C128, 0, 30, P.PRX_PLAIN)
+    info = P.prx_plan_get_info(pl)
+    assert info["passes"] == info["plain_passes"] == 30 and info["kernel_rotations"] == 30
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)

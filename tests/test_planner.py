@@ -1,0 +1,160 @@
+"""Planner checks on the host: the exported plan, executed by an independent
+interpreter (tests/plan_interp.py), reproduces the oracle; kernel rotations
+compose to the schedule; commuting reorders are legal; passes are closed."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import statevector as sv
+from paper_2504_17881_amd import prx as P
+from plan_interp import run_plan
+
+
+def _sched(n, x, z, phi):
+    return P.prx_sched_from_rotations(n, x, z, phi)
+
+
+def _check_composition(plan, x, z, phi, commuting=False):
+    info = P.prx_plan_get_info(plan)
+    rots = [P.prx_plan_rotation(plan, i) for i in range(info["kernel_rotations"])]
+    # every schedule rotation appears once, possibly as two half angles
+    by_src = {}
+    for r in rots:
+        by_src.setdefault(r["source"], []).append(r)
+    assert sorted(by_src) == list(range(len(x)))
+    for j, rs in by_src.items():
+        assert all(r["x"] == x[j] and r["z"] == z[j] for r in rs)
+        assert len(rs) in (1, 2)
+        tot = sum(r["phi"] for r in rs)
+        assert abs(tot - phi[j]) <= 4e-16 * max(1.0, abs(phi[j]))
+        if len(rs) == 2:
+            assert abs(math.cos(phi[j])) < 0.5 and rs[0]["phi"] == rs[1]["phi"]
+        assert all(abs(math.cos(r["phi"])) >= 0.5 or info["passes"] == info["plain_passes"]
+                   for r in rs)
+    order = [r["source"] for r in rots]
+    if not commuting:
+        assert order == sorted(order)
+    else:
+        # any inversion must be between commuting rotations
+        for a in range(len(order)):
+            for b in range(a + 1, len(order)):
+                if order[a] > order[b]:
+                    ra, rb = rots[a], rots[b]
+                    sym = bin((ra["x"] & rb["z"]) ^ (ra["z"] & rb["x"])).count("1")
+                    assert sym % 2 == 0
+
+
+def _check_closure(plan, n):
+    info = P.prx_plan_get_info(plan)
+    for pi in range(info["passes"]):
+        ps = P.prx_plan_pass(plan, pi)
+        rots = [P.prx_plan_rotation(plan, i)
+                for i in range(ps["rot_begin"], ps["rot_begin"] + ps["rot_count"])]
+        if ps["kind"] == 1:
+            basis = ps["basis"][:ps["m"]]
+            for r in rots:
+                assert r["x"] == 0 or r["x"] == basis[r["slot"]]
+        elif ps["kind"] == 2:
+            b, g = ps["b"], ps["g"]
+            span = {ps["vcomb"][v] for v in range(1 << g)}
+            for r in rots:
+                assert (r["x"] >> b) in span
+
+
+@pytest.mark.parametrize("n,M,dtype,opts", [
+    (12, 300, P.PRX_C128, None),
+    (13, 300, P.PRX_C128, dict(tile_qubits=10, chunk_rank=3)),
+    (12, 200, P.PRX_C64, dict(tile_qubits=11, chunk_rank=4, max_virtual=1)),
+    (11, 150, P.PRX_C128, dict(span_max=5)),
+])
+def test_interpreter_matches_oracle_random(n, M, dtype, opts):
+    x, z, phi = synth.random_pauli_rotations(n, M, seed=n + M)
+    psi0 = synth.gaussian_state(n, 2)
+    s = _sched(n, x, z, phi)
+    pl = P.prx_plan_create(s, n, dtype, 0, M, P.PRX_FUSED, opts)
+    _check_composition(pl, x, z, phi)
+    _check_closure(pl, n)
+    ref = sv.c_apply_rotations(psi0, x, z, phi)
+    out = run_plan(pl, psi0, n)
+    tol = 1e-11 if dtype == P.PRX_C128 else 5e-5
+    assert np.linalg.norm(out - ref) <= tol
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+
+
+@pytest.mark.parametrize("opts", [None, dict(max_virtual=1), dict(tile_qubits=10, chunk_rank=4),
+                                  dict(tile_qubits=12, chunk_rank=5), dict(commuting=1),
+                                  dict(max_fuse=7)])
+def test_interpreter_matches_oracle_jw_trotter(opts):
+    n = 14
+    x, z, h = synth.jw_hamiltonian(n, 300, 7)
+    H = P.prx_ham_create(n, x, z, h)
+    s = P.prx_sched_trotter(H, 1, 2.0, 2, P.PRX_REORDER_SUFFIX)
+    _, rx, rz, rp = P.prx_sched_view(s)
+    pl = P.prx_plan_create(s, n, P.PRX_C128, 0, len(rx), P.PRX_FUSED, opts)
+    info = P.prx_plan_get_info(pl)
+    assert info["tile_passes"] > 0
+    _check_composition(pl, rx, rz, rp, commuting=bool(opts and opts.get("commuting")))
+    _check_closure(pl, n)
+    psi0 = synth.gaussian_state(n, 3)
+    ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+    out = run_plan(pl, psi0, n)
+    assert np.linalg.norm(out - ref) <= 1e-11
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
+
+
+def test_interpreter_renormalised_c64_plan():
+    n = 13
+    x, z, h = synth.jw_hamiltonian(n, 200, 8)
+    H = P.prx_ham_create(n, x, z, h)
+    s = P.prx_sched_trotter(H, 1, 1.0, 2, P.PRX_REORDER_SUFFIX)
+    _, rx, rz, rp = P.prx_sched_view(s)
+    pl = P.prx_plan_create(s, n, P.PRX_C64, 0, len(rx), P.PRX_FUSED)
+    passes = [P.prx_plan_pass(pl, i) for i in range(P.prx_plan_get_info(pl)["passes"])]
+    assert any(p["norm_out"] for p in passes)
+    # the hand-off links consecutive fused passes
+    for a, b in zip(passes, passes[1:]):
+        assert a["norm_out"] == b["renorm_in"]
+    psi0 = synth.gaussian_state(n, 4)
+    ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+    out = run_plan(pl, psi0, n)
+    assert np.linalg.norm(out - ref) <= 1e-6
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
+
+
+def test_diagonal_only_and_identity_rotations():
+    n = 10
+    rng = np.random.default_rng(3)
+    z = rng.integers(0, 1 << n, size=40).astype(np.uint64)
+    z[5] = 0
+    x = np.zeros(40, dtype=np.uint64)
+    phi = rng.uniform(-3, 3, size=40)
+    s = _sched(n, x, z, phi)
+    pl = P.prx_plan_create(s, n, P.PRX_C128, 0, 40, P.PRX_FUSED)
+    psi0 = synth.gaussian_state(n, 5)
+    ref = sv.c_apply_rotations(psi0, x, z, phi)
+    assert np.linalg.norm(run_plan(pl, psi0, n) - ref) <= 1e-12
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+
+
+def test_sub_range_plans_compose():
+    n, M = 12, 120
+    x, z, phi = synth.random_pauli_rotations(n, M, seed=9)
+    s = _sched(n, x, z, phi)
+    psi0 = synth.gaussian_state(n, 6)
+    mid = 47
+    a = P.prx_plan_create(s, n, P.PRX_C128, 0, mid, P.PRX_FUSED)
+    b = P.prx_plan_create(s, n, P.PRX_C128, mid, M, P.PRX_FUSED)
+    out = run_plan(b, run_plan(a, psi0, n), n)
+    ref = sv.c_apply_rotations(psi0, x, z, phi)
+    assert np.linalg.norm(out - ref) <= 1e-11
+    for p in (a, b):
+        P.prx_plan_destroy(p)
+    P.prx_sched_destroy(s)
