@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Benchmark: amplitude updates/s and HBM roofline at n=32, FP32 fused vs FP64 plain.
+
+Workload (precision workload): synthetic Jordan-Wigner-shaped Hamiltonian,
+n = 32, L = 5000 terms (seed 0), lexicographically ordered terms,
+first-order Trotter with t = 0.5 and 4 steps (2*10^4 rotations), initial
+basis state with the low 16 bits set.  One bench step is one Trotter step
+(5000 rotations) applied by the fused complex64 path with FP64
+renormalisation, followed by the overlap with the initial basis state.
+
+Reported:
+  value        amplitude updates per second of the timed steps
+               (updates = rotations * 2^n; inputs resident in HBM);
+  roofline     the dominant kernel (largest share of the timed steps'
+               kernel time): algorithmic bytes per launch (2 * 2^n * 8 B,
+               one read and one write of the state) over its average
+               launch duration from HIP events recorded around every pass;
+  fp64_plain   the complex128 single-rotation sweep on the same schedule
+               (first `--plain-rotations` rotations), for the 2x comparison;
+  cpu_baseline the FP64 CPU oracle on the first rotations of the same
+               schedule and state, on this host's cores.
+
+    python bench.py [--gpus 1] [--steps 4] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+METRIC = "amplitude-updates/s and %HBM peak at n=32, FP32-fused vs FP64-plain"
+
+
+def kernel_symbol(ps: dict, dtype_name: str) -> str:
+    if ps["kind"] == 1:
+        return f"k_span<{dtype_name},{ps['m']}>"
+    if ps["kind"] == 2:
+        return f"k_tile<{dtype_name},{ps['B']},{ps['m']}>"
+    return f"k_plain<{dtype_name}>"
+
+
+def kernel_sources_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2504_17881_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_trotter1_n32_c64.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources") != kernel_sources_digest():
+        return None
+    if vals.get("kernel") != kernel:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(x, z, phi, n: int, k0: int, budget_s: float, max_rot: int):
+    """The oracle as it stands, on the first rotations of the schedule."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    from oracle import statevector as sv
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[k0] = 1.0
+    work = np.empty_like(psi)
+    done = 0
+    t0 = time.perf_counter()
+    while done < max_rot:
+        sv.c_apply_rotations(psi, x[done:done + 1], z[done:done + 1], phi[done:done + 1],
+                             out=psi, work=work)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {
+        "value": done * float(1 << n) / dt,
+        "unit": "amplitude-updates/s",
+        "cores": sv.c_threads(),
+        "kind": "oracle",
+        "sample": (f"first {done} rotation(s) of the same n={n} schedule from the same basis "
+                   f"state, FP64 C oracle (scatter form, OpenMP), {dt:.1f} s"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--plain-rotations", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--fused-only", action="store_true",
+                    help="skip the FP64-plain comparator (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path is a "
+              "single-device kernel and this build has no multi-GPU path.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    import synth
+    from paper_2504_17881_amd import prx as P
+
+    w = synth.WORKLOADS["trotter1_n32"]
+    n = args.n
+    L, t, S = w["L"], w["t"], w["steps"]
+    x, z, h = synth.jw_hamiltonian(n, L, w["ham_seed"])
+    H = P.prx_ham_create(n, x, z, h)
+    sched = P.prx_sched_trotter(H, 1, t, S, P.PRX_REORDER_SUFFIX)
+    _, sx, sz, sphi = P.prx_sched_view(sched)
+    k0 = synth.basis_index(n)
+    dev = torch.device("cuda:0")
+    print(f"[bench] n={n} L={L} rotations={len(sx)}", file=sys.stderr, flush=True)
+
+    # ---------------- fused complex64: one plan per Trotter step (identical steps)
+    plan = P.prx_plan_create(sched, n, P.PRX_C64, 0, L, P.PRX_FUSED)
+    info = P.prx_plan_get_info(plan)
+    passes = [P.prx_plan_pass(plan, i) for i in range(info["passes"])]
+    names = [kernel_symbol(p, "float") for p in passes]
+    ws = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device=dev)
+    P.prx_plan_upload(plan, ws)
+    psi = torch.zeros(1 << n, dtype=torch.complex64, device=dev)
+    psi[k0] = 1.0
+    bra = k0
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        P.prx_plan_execute_timed(plan, psi, ws)
+        P.prx_amplitude(psi, n, P.PRX_C64, bra)
+    torch.cuda.synchronize()
+    print(f"[bench] fused c64: {info['passes']} passes/step, mean fuse "
+          f"{info['mean_fuse']:.2f}", file=sys.stderr, flush=True)
+
+    per_kernel = {}
+    renorm_total = 0.0
+    ov = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pm, rm = P.prx_plan_execute_timed(plan, psi, ws)
+        ov = P.prx_amplitude(psi, n, P.PRX_C64, bra)  # <k0|psi>
+        for nm, ms in zip(names, pm):
+            a = per_kernel.setdefault(nm, [0, 0.0])
+            a[0] += 1
+            a[1] += float(ms)
+        renorm_total += float(rm.sum())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    updates = args.steps * L * float(1 << n)
+    value = updates / wall
+    state_bytes = float(1 << n) * 8
+    bytes_per_pass = 2.0 * state_bytes
+    dom = max(per_kernel.items(), key=lambda kv: kv[1][1])
+    dom_name, (dom_cnt, dom_ms) = dom
+    dom_avg_ms = dom_ms / dom_cnt
+    achieved = bytes_per_pass / (dom_avg_ms * 1e-3) / 1e9
+    traffic = read_traffic(dom_name)
+    all_pass_bw = args.steps * info["passes"] * bytes_per_pass / wall / 1e9
+    P.prx_plan_destroy(plan)
+    del psi, ws
+    torch.cuda.empty_cache()
+
+    # ---------------- FP64 plain comparator (complex128, one sweep per rotation)
+    fp64 = None
+    if not args.fused_only:
+        R = min(args.plain_rotations, len(sx))
+        pplan = P.prx_plan_create(sched, n, P.PRX_C128, 0, R, P.PRX_PLAIN)
+        pinfo = P.prx_plan_get_info(pplan)
+        pws = torch.empty(pinfo["workspace_bytes"], dtype=torch.uint8, device=dev)
+        P.prx_plan_upload(pplan, pws)
+        psi2 = torch.zeros(1 << n, dtype=torch.complex128, device=dev)
+        psi2[k0] = 1.0
+        warm = P.prx_plan_create(sched, n, P.PRX_C128, 0, 4, P.PRX_PLAIN)
+        wws = torch.empty(P.prx_plan_get_info(warm)["workspace_bytes"], dtype=torch.uint8,
+                          device=dev)
+        P.prx_plan_upload(warm, wws)
+        P.prx_plan_execute(warm, psi2, wws)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        pm, _ = P.prx_plan_execute_timed(pplan, psi2, pws)
+        torch.cuda.synchronize()
+        pwall = time.perf_counter() - tp0
+        p_updates = R * float(1 << n)
+        avg_ms = float(pm.mean())
+        fp64 = {
+            "value": p_updates / pwall,
+            "unit": "amplitude-updates/s",
+            "rotations": R,
+            "kernel": "k_plain_pair<double,4> / k_plain_diag<double,4>",
+            "avg_launch_ms": avg_ms,
+            "hbm_frac": (2.0 * float(1 << n) * 16 / (avg_ms * 1e-3) / 1e9) / HBM_PEAK_GBS,
+            "fused_c64_over_plain_c128": value / (p_updates / pwall),
+        }
+        P.prx_plan_destroy(pplan)
+        P.prx_plan_destroy(warm)
+        del psi2, pws, wws
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(sx, sz, sphi, n, k0, args.cpu_budget, 4)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "amplitude-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"trotter1_n{n}: synthetic JW-shaped H, n={n}, L={L}, first-order "
+                         f"Trotter t={t}, {S} steps in the run, lexicographic (SUFFIX) term "
+                         "order, complex64 fused with FP64 renormalisation; one step = one "
+                         "Trotter step (5000 rotations) + basis overlap"),
+            "n": n, "L": L, "rotations_per_step": L,
+            "passes_per_step": info["passes"], "mean_fuse": info["mean_fuse"],
+            "span_passes": info["span_passes"], "tile_passes": info["tile_passes"],
+            "plain_passes": info["plain_passes"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": dom_name,
+            "launches": dom_cnt,
+            "avg_launch_ms": dom_avg_ms,
+            "bytes_per_launch": bytes_per_pass,
+            "all_passes_GBps": all_pass_bw,
+        },
+        "kernels": {k: {"launches": c, "total_ms": ms, "avg_ms": ms / c}
+                    for k, (c, ms) in sorted(per_kernel.items())},
+        "renorm_ms_total": renorm_total,
+        "overlap_final": [ov.real, ov.imag] if ov is not None else None,
+        "fp64_plain": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

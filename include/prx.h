@@ -187,6 +187,14 @@ prx_status prx_plan_upload(const prx_plan *plan, void *ws, size_t ws_bytes, void
 prx_status prx_plan_execute(const prx_plan *plan, void *psi, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* As prx_plan_execute, additionally recording a HIP event before and after
+ * every pass kernel and after its renormalisation hand-off, then waiting
+ * for the stream.  pass_ms[i] receives the duration of pass i's kernel and
+ * renorm_ms[i] (nullable) that of its hand-off (0 when it has none); both
+ * are host arrays with one entry per pass. */
+prx_status prx_plan_execute_timed(const prx_plan *plan, void *psi, void *ws, size_t ws_bytes,
+                                  void *stream, float *pass_ms, float *renorm_ms);
+
 /* Plan inspection (read-only views for tests and tools).
  *
  * Passes: kind 0 = single-rotation sweep, 1 = span pass (one chunk in the
@@ -275,32 +283,52 @@ prx_status prx_renormalize(void *psi, int n, prx_dtype dtype, void *ws, size_t w
 /* ------------------------------------------------------------------ */
 
 typedef struct prx_batch prx_batch;
+typedef struct prx_graph prx_graph;
 
-/* Plans S independent runs: sample s applies sched[s] to the state psi[s]
- * (device, 2^n[s] of dtype; distinct, non-overlapping buffers) and reports
- * <basis_idx[s]|psi_s>.  All samples run in one persistent kernel launch
- * that pulls (sample, pass, slice) work items from a queue; per-sample
- * counters order the passes of each sample.  Host only; no device calls.
- * INVALID if S = 0, an n[s] is outside [6, 34], or basis_idx[s] >= 2^n[s]. */
+/* Plans S independent runs: sample s applies sched[s] to its own state
+ * (2^n[s] amplitudes of dtype) and reports <basis_idx[s]|psi_s>.  Each
+ * sample's schedule is segmented into span passes of a fixed rank, and all
+ * samples run in one persistent kernel that pulls (sample, pass, slice) work
+ * items from a queue in pass-round order; a per-sample completion counter
+ * orders the passes of each sample.  Host only; no device calls.  INVALID if
+ * S = 0, an n[s] is outside [6, 34], sched[s]->n != n[s], or basis_idx[s] >=
+ * 2^n[s]. */
 prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sched,
                             prx_dtype dtype, const uint64_t *basis_idx, prx_batch **out);
 size_t prx_batch_workspace_bytes(const prx_batch *b);
-/* Uploads the tables, like prx_plan_upload. */
-prx_status prx_batch_upload(const prx_batch *b, void *ws, size_t ws_bytes, void *stream);
-/* Enqueues the persistent launch and the overlap read-out (asynchronous).
- * psi[s] are device pointers (host array of S).  Resets the queue itself,
- * so it may be replayed, including from a captured graph.  overlaps_dev is
- * a device array of 2*S doubles receiving (re, im) per sample. */
-prx_status prx_batch_execute(const prx_batch *b, void *const *psi, void *ws, size_t ws_bytes,
+/* Records the device state pointers psi[s] (host array of S distinct,
+ * non-overlapping, 16-byte aligned buffers) and copies the batch tables into
+ * `ws`; waits for the copies. */
+prx_status prx_batch_upload(prx_batch *b, void *const *psi, void *ws, size_t ws_bytes,
+                            void *stream);
+/* Enqueues, on `stream`, three kernels and nothing else: a reset of the
+ * queue and counters, the persistent kernel, and the overlap read-out into
+ * overlaps_dev (device array of 2*S doubles, (re, im) per sample).  It can
+ * therefore be replayed and captured in a graph. */
+prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
                              double *overlaps_dev, void *stream);
+/* Waits for the stream and reports PRX_ERR_HIP if the persistent kernel gave
+ * up on a dependency wait (a bounded spin; not expected to trigger). */
+prx_status prx_batch_check(const prx_batch *b, const void *ws, void *stream);
 void prx_batch_destroy(prx_batch *b);
 
-/* One-call form: create, upload, execute, copy the 2*S overlaps to the
- * host array `overlaps`, synchronise, destroy. */
+/* One-call form: create, upload, execute, check, copy the 2*S overlaps to
+ * the host array `overlaps`, destroy.  ws must hold
+ * prx_batch_workspace_bytes + 2*S doubles (rounded up to 256 bytes). */
 prx_status prx_batch_run(size_t S, void *const *psi, const int *n,
                          const prx_sched *const *sched, prx_dtype dtype,
                          const uint64_t *basis_idx, double *overlaps, void *ws,
                          size_t ws_bytes, void *stream);
+
+/* HIP graphs of a batch execution or of a plan's pass sequence, captured on
+ * `stream` (which must not be the default stream) and instantiated; replay
+ * with prx_graph_launch on any stream. */
+prx_status prx_batch_graph(const prx_batch *b, void *ws, size_t ws_bytes,
+                           double *overlaps_dev, void *stream, prx_graph **out);
+prx_status prx_plan_graph(const prx_plan *plan, void *psi, void *ws, size_t ws_bytes,
+                          void *stream, prx_graph **out);
+prx_status prx_graph_launch(const prx_graph *g, void *stream);
+void prx_graph_destroy(prx_graph *g);
 
 /* ------------------------------------------------------------------ */
 /* Autotuning.                                                         */

@@ -1,4 +1,4 @@
-// Internal declarations shared by the host planner (host.cpp) and the HIP
+// Internal declarations shared by the host code (sched.cpp, plan.cpp, tune.cpp) and the HIP
 // kernels (kernels.hip, batch.hip).  Not part of the public ABI.
 #pragma once
 
@@ -94,6 +94,15 @@ struct PlainArgs {
     double c;        // cos(phi)
     double beta;     // signed magnitude of beta
 };
+
+// Autotune cache (tune.cpp), keyed by (arch, n, dtype).
+bool tune_lookup(int n, prx_dtype dt, prx_plan_opts *out);
+void tune_store(int n, prx_dtype dt, const prx_plan_opts &o);
+
+struct PlanCfg;
+// Plan with explicit internal settings (batched plans: span-only, fixed rank).
+prx_status plan_create_cfg(const prx_sched *sched, int n, prx_dtype dtype, const PlanCfg &cfg,
+                           prx_plan **out);
 
 // ------------------------------------------------------------ launchers
 // All enqueue on `stream` and return hipGetLastError() of the launch.

@@ -62,6 +62,8 @@ struct PlanCfg {
     int max_virtual = 2;
     int renorm_every = 1;
     bool commuting = false;
+    bool span_only = false;  // batched plans: every pass is a span pass ...
+    int pad_rank = 0;        // ... whose basis is padded to exactly this rank
 };
 
 // Workspace regions (byte offsets, 256-aligned).

@@ -211,8 +211,15 @@ struct Builder {
             }
         }
         if (basis.empty()) {  // diagonal-only run: any direction serves as the basis
-            basis.push_back(1);
-            g.add(1);
+            basis.push_back(1ull << (P.n - 1));
+            g.add(1ull << (P.n - 1));
+        }
+        // fixed-rank plans: pad with unused high unit directions
+        for (int q = P.n - 1; (int)basis.size() < cfg.pad_rank && q >= 0; --q) {
+            if (!g.contains(1ull << q)) {
+                g.add(1ull << q);
+                basis.push_back(1ull << q);
+            }
         }
         Pass ps;
         ps.kind = kSpan;
@@ -364,6 +371,11 @@ struct Builder {
         for (size_t p = P.begin; p < end; ++p) emit_plain(p);
     }
 
+    void run_span_only() {
+        size_t p = P.begin;
+        while (p < end) p = emit_span(p);
+    }
+
     void run_fused() {
         const bool tile_ok = P.n >= cfg.B + 1 && tile_supported(P.dtype, cfg.B, cfg.m);
         size_t p = P.begin;
@@ -418,14 +430,6 @@ static void default_cfg(prx_dtype dt, PlanCfg &c) {
     c.commuting = false;
 }
 
-// autotune cache: key "gfx950/<n>/<dtype>"
-static std::mutex g_tune_mu;
-static std::map<std::string, prx_plan_opts> g_tune;
-
-static std::string tune_key(int n, prx_dtype dt) {
-    return "gfx950/" + std::to_string(n) + "/" + (dt == PRX_C64 ? "c64" : "c128");
-}
-
 static void apply_opts(const prx_plan_opts *o, PlanCfg &c) {
     if (!o) return;
     if (o->tile_qubits) c.B = o->tile_qubits;
@@ -452,13 +456,9 @@ static void pack_records(prx_plan &P, const std::vector<RotRecD> &recs) {
     }
 }
 
-}  // namespace prx
-
-extern "C" {
-
-prx_status prx_plan_create(const prx_sched *sched, int n, prx_dtype dtype, size_t begin,
-                           size_t end, prx_kernel kernel, const prx_plan_opts *opts,
-                           prx_plan **out) {
+static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtype, size_t begin,
+                                   size_t end, prx_kernel kernel, const prx_plan_opts *opts,
+                                   const PlanCfg *internal, prx_plan **out) {
     if (!sched || !out) return fail(PRX_ERR_INVALID, "null pointer");
     if (dtype != PRX_C64 && dtype != PRX_C128) return fail(PRX_ERR_INVALID, "bad dtype");
     if (kernel < PRX_PLAIN || kernel > PRX_AUTO) return fail(PRX_ERR_INVALID, "bad kernel");
@@ -475,11 +475,11 @@ prx_status prx_plan_create(const prx_sched *sched, int n, prx_dtype dtype, size_
         P->begin = 0;
         default_cfg(dtype, P->cfg);
         if (kernel == PRX_AUTO) {
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            auto it = g_tune.find(tune_key(n, dtype));
-            if (it != g_tune.end()) apply_opts(&it->second, P->cfg);
+            prx_plan_opts t;
+            if (tune_lookup(n, dtype, &t)) apply_opts(&t, P->cfg);
         }
         apply_opts(opts, P->cfg);
+        if (internal) P->cfg = *internal;
         const bool fused = kernel != PRX_PLAIN;
         if (fused) {
             if (!tile_supported(dtype, P->cfg.B, P->cfg.m) && P->n > P->cfg.B) {
@@ -504,7 +504,9 @@ prx_status prx_plan_create(const prx_sched *sched, int n, prx_dtype dtype, size_
         P->end = P->rots.size();
         Builder bld(*P, P->end);
         // span passes need 2^(n - m) >= 1 cosets; tiny states fall back to plain
-        if (!fused || n < 4)
+        if (P->cfg.span_only)
+            bld.run_span_only();
+        else if (!fused || n < 4)
             bld.run_plain();
         else {
             if (P->cfg.span_m > n - 1) P->cfg.span_m = std::max(1, n - 1);
@@ -553,6 +555,22 @@ prx_status prx_plan_create(const prx_sched *sched, int n, prx_dtype dtype, size_
     return PRX_OK;
 }
 
+prx_status plan_create_cfg(const prx_sched *sched, int n, prx_dtype dtype, const PlanCfg &cfg,
+                           prx_plan **out) {
+    return plan_create_impl(sched, n, dtype, 0, sched ? sched->x.size() : 0, PRX_FUSED, nullptr,
+                            &cfg, out);
+}
+
+}  // namespace prx
+
+extern "C" {
+
+prx_status prx_plan_create(const prx_sched *sched, int n, prx_dtype dtype, size_t begin,
+                           size_t end, prx_kernel kernel, const prx_plan_opts *opts,
+                           prx_plan **out) {
+    return plan_create_impl(sched, n, dtype, begin, end, kernel, opts, nullptr, out);
+}
+
 prx_status prx_plan_get_info(const prx_plan *P, prx_plan_info *o) {
     if (!P || !o) return fail(PRX_ERR_INVALID, "null pointer");
     std::memset(o, 0, sizeof(*o));
@@ -591,33 +609,38 @@ prx_status prx_plan_upload(const prx_plan *P, void *ws, size_t ws_bytes, void *s
     return PRX_OK;
 }
 
-prx_status prx_plan_execute(const prx_plan *P, void *psi, void *ws, size_t ws_bytes,
-                            void *stream) {
+}  // extern "C"
+
+namespace prx {
+
+// Enqueues the plan; with `ev` non-null, records ev[3i] before pass i,
+// ev[3i+1] after its kernel and ev[3i+2] after its hand-off.
+static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws_bytes,
+                               hipStream_t s, hipEvent_t *ev) {
     if (!P || !psi || !ws) return fail(PRX_ERR_INVALID, "null pointer");
     if (ws_bytes < P->ws.total) return fail(PRX_ERR_INVALID, "workspace too small");
     if (((uintptr_t)psi & 15) || ((uintptr_t)ws & 255))
         return fail(PRX_ERR_INVALID, "misaligned state or workspace");
-    hipStream_t s = (hipStream_t)stream;
     char *base = (char *)ws;
     const void *rots = base + P->ws.rot_off;
     const ChunkRec *chunks = (const ChunkRec *)(base + P->ws.chunk_off);
     double *part = (double *)(base + P->ws.part_off);
     double *scal = (double *)(base + P->ws.scal_off);
-    const size_t rsz = P->dtype == PRX_C64 ? sizeof(RotRec<float>) : sizeof(RotRec<double>);
-    (void)rsz;
-    for (const Pass &ps : P->passes) {
+    for (size_t i = 0; i < P->passes.size(); ++i) {
+        const Pass &ps = P->passes[i];
         const double *rin = ps.renorm_in ? scal : nullptr;
         double *nout = ps.norm_out ? part : nullptr;
         unsigned blocks = 0;
         hipError_t e = hipSuccess;
+        if (ev) PRX_HIP(hipEventRecord(ev[3 * i], s));
         if (ps.kind == kPlain) {
             e = launch_plain(P->dtype, psi, plain_args(P->n, P->rots[ps.r0]), s);
         } else if (ps.kind == kSpan) {
             SpanArgs a;
             std::memset(&a, 0, sizeof(a));
-            for (int i = 0; i < ps.m; ++i) {
-                a.basis[i] = ps.basis[i];
-                a.pivot[i] = ps.pivot[i];
+            for (int k = 0; k < ps.m; ++k) {
+                a.basis[k] = ps.basis[k];
+                a.pivot[k] = ps.pivot[k];
             }
             a.rot_begin = (uint32_t)ps.r0;
             a.rot_count = (uint32_t)(ps.r1 - ps.r0);
@@ -627,8 +650,8 @@ prx_status prx_plan_execute(const prx_plan *P, void *psi, void *ws, size_t ws_by
         } else {
             TileArgs a;
             std::memset(&a, 0, sizeof(a));
-            for (int i = 0; i < (1 << ps.g); ++i) a.vcomb[i] = ps.vcomb[i];
-            for (int i = 0; i < ps.g; ++i) a.tpivot[i] = ps.tpivot[i];
+            for (int k = 0; k < (1 << ps.g); ++k) a.vcomb[k] = ps.vcomb[k];
+            for (int k = 0; k < ps.g; ++k) a.tpivot[k] = ps.tpivot[k];
             a.n = P->n;
             a.b = ps.b;
             a.g = ps.g;
@@ -638,13 +661,56 @@ prx_status prx_plan_execute(const prx_plan *P, void *psi, void *ws, size_t ws_by
             e = launch_tile(P->dtype, ps.B, ps.m, psi, a, rots, chunks, rin, nout, s, &blocks);
         }
         if (e != hipSuccess) return hip_fail(e, "pass launch");
+        if (ev) PRX_HIP(hipEventRecord(ev[3 * i + 1], s));
         if (ps.norm_out) {
             e = launch_renorm_finish(part, blocks, scal, s);
             if (e != hipSuccess) return hip_fail(e, "renorm launch");
         }
+        if (ev) PRX_HIP(hipEventRecord(ev[3 * i + 2], s));
     }
     return PRX_OK;
 }
+
+}  // namespace prx
+
+prx_status prx_plan_execute(const prx_plan *P, void *psi, void *ws, size_t ws_bytes,
+                            void *stream) {
+    return execute_impl(P, psi, ws, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+prx_status prx_plan_execute_timed(const prx_plan *P, void *psi, void *ws, size_t ws_bytes,
+                                  void *stream, float *pass_ms, float *renorm_ms) {
+    if (!P || !pass_ms) return fail(PRX_ERR_INVALID, "null pointer");
+    const size_t np = P->passes.size();
+    std::vector<hipEvent_t> ev(3 * np, nullptr);
+    prx_status st = PRX_OK;
+    for (size_t i = 0; i < ev.size() && st == PRX_OK; ++i) {
+        hipError_t e = hipEventCreate(&ev[i]);
+        if (e != hipSuccess) st = hip_fail(e, "hipEventCreate");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (st == PRX_OK) st = execute_impl(P, psi, ws, ws_bytes, s, ev.data());
+    if (st == PRX_OK) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    for (size_t i = 0; i < np && st == PRX_OK; ++i) {
+        float a = 0.f, b = 0.f;
+        hipError_t e = hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "hipEventElapsedTime");
+            break;
+        }
+        pass_ms[i] = a;
+        if (renorm_ms) renorm_ms[i] = P->passes[i].norm_out ? b : 0.f;
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
+}
+
+extern "C" {
 
 prx_status prx_plan_pass(const prx_plan *P, size_t i, prx_pass_info *o) {
     if (!P || !o) return fail(PRX_ERR_INVALID, "null pointer");

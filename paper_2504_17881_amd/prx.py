@@ -119,6 +119,8 @@ _sig("prx_plan_get_info", _st, _vp, ctypes.POINTER(prx_plan_info))
 _sig("prx_plan_destroy", None, _vp)
 _sig("prx_plan_upload", _st, _vp, _vp, _sz, _vp)
 _sig("prx_plan_execute", _st, _vp, _vp, _vp, _sz, _vp)
+_sig("prx_plan_execute_timed", _st, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_float),
+     ctypes.POINTER(ctypes.c_float))
 _sig("prx_plan_pass", _st, _vp, _sz, ctypes.POINTER(prx_pass_info))
 _sig("prx_plan_chunk", _st, _vp, _sz, ctypes.POINTER(prx_chunk_info))
 _sig("prx_plan_rotation", _st, _vp, _sz, ctypes.POINTER(prx_rot_info))
@@ -132,11 +134,16 @@ _sig("prx_renormalize", _st, _vp, _i, _i, _vp, _sz, _vp)
 _sig("prx_batch_create", _st, _sz, ctypes.POINTER(_i), ctypes.POINTER(_vp), _i, _u64p,
      ctypes.POINTER(_vp))
 _sig("prx_batch_workspace_bytes", _sz, _vp)
-_sig("prx_batch_upload", _st, _vp, _vp, _sz, _vp)
-_sig("prx_batch_execute", _st, _vp, ctypes.POINTER(_vp), _vp, _sz, _vp, _vp)
+_sig("prx_batch_upload", _st, _vp, ctypes.POINTER(_vp), _vp, _sz, _vp)
+_sig("prx_batch_execute", _st, _vp, _vp, _sz, _vp, _vp)
+_sig("prx_batch_check", _st, _vp, _vp, _vp)
 _sig("prx_batch_destroy", None, _vp)
 _sig("prx_batch_run", _st, _sz, ctypes.POINTER(_vp), ctypes.POINTER(_i), ctypes.POINTER(_vp),
      _i, _u64p, _dp, _vp, _sz, _vp)
+_sig("prx_batch_graph", _st, _vp, _vp, _sz, _vp, _vp, ctypes.POINTER(_vp))
+_sig("prx_plan_graph", _st, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp))
+_sig("prx_graph_launch", _st, _vp, _vp)
+_sig("prx_graph_destroy", None, _vp)
 _sig("prx_autotune", _st, _vp, _i, _i, _vp, _vp, _sz, _vp, ctypes.POINTER(prx_plan_opts),
      ctypes.POINTER(_i))
 _sig("prx_autotune_save", _st, ctypes.c_char_p)
@@ -317,6 +324,18 @@ def prx_plan_execute(plan: int, psi, ws, stream=None, ws_bytes=None) -> None:
                                  _stream(stream)))
 
 
+def prx_plan_execute_timed(plan: int, psi, ws, stream=None, ws_bytes=None):
+    """Executes and waits; returns (pass_ms, renorm_ms) numpy float32 arrays."""
+    npass = prx_plan_get_info(plan)["passes"]
+    pm = np.zeros(max(npass, 1), dtype=np.float32)
+    rm = np.zeros(max(npass, 1), dtype=np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    _check(_lib.prx_plan_execute_timed(plan, _ptr(psi), _ptr(ws), _nbytes(ws, ws_bytes),
+                                       _stream(stream), pm.ctypes.data_as(fp),
+                                       rm.ctypes.data_as(fp)))
+    return pm[:npass], rm[:npass]
+
+
 def prx_plan_pass(plan: int, i: int) -> dict:
     o = prx_pass_info()
     _check(_lib.prx_plan_pass(plan, i, ctypes.byref(o)))
@@ -403,14 +422,18 @@ def prx_batch_workspace_bytes(batch: int) -> int:
     return int(_lib.prx_batch_workspace_bytes(batch))
 
 
-def prx_batch_upload(batch: int, ws, stream=None, ws_bytes=None) -> None:
-    _check(_lib.prx_batch_upload(batch, _ptr(ws), _nbytes(ws, ws_bytes), _stream(stream)))
-
-
-def prx_batch_execute(batch: int, psis, ws, overlaps_dev, stream=None, ws_bytes=None) -> None:
+def prx_batch_upload(batch: int, psis, ws, stream=None, ws_bytes=None) -> None:
     pa = _ptr_array(psis)
-    _check(_lib.prx_batch_execute(batch, pa, _ptr(ws), _nbytes(ws, ws_bytes),
-                                  _ptr(overlaps_dev), _stream(stream)))
+    _check(_lib.prx_batch_upload(batch, pa, _ptr(ws), _nbytes(ws, ws_bytes), _stream(stream)))
+
+
+def prx_batch_execute(batch: int, ws, overlaps_dev, stream=None, ws_bytes=None) -> None:
+    _check(_lib.prx_batch_execute(batch, _ptr(ws), _nbytes(ws, ws_bytes), _ptr(overlaps_dev),
+                                  _stream(stream)))
+
+
+def prx_batch_check(batch: int, ws, stream=None) -> None:
+    _check(_lib.prx_batch_check(batch, _ptr(ws), _stream(stream)))
 
 
 def prx_batch_destroy(batch: int) -> None:
@@ -428,6 +451,28 @@ def prx_batch_run(psis, n_list, scheds, dtype: int, basis_idx, ws, stream=None,
     _check(_lib.prx_batch_run(S, pa, na, sa, dtype, bp, out.ctypes.data_as(_dp), _ptr(ws),
                               _nbytes(ws, ws_bytes), _stream(stream)))
     return out[0::2] + 1j * out[1::2]
+
+
+def prx_batch_graph(batch: int, ws, overlaps_dev, stream, ws_bytes=None) -> int:
+    out = _vp()
+    _check(_lib.prx_batch_graph(batch, _ptr(ws), _nbytes(ws, ws_bytes), _ptr(overlaps_dev),
+                                _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
+def prx_plan_graph(plan: int, psi, ws, stream, ws_bytes=None) -> int:
+    out = _vp()
+    _check(_lib.prx_plan_graph(plan, _ptr(psi), _ptr(ws), _nbytes(ws, ws_bytes), _stream(stream),
+                               ctypes.byref(out)))
+    return out.value
+
+
+def prx_graph_launch(graph: int, stream=None) -> None:
+    _check(_lib.prx_graph_launch(graph, _stream(stream)))
+
+
+def prx_graph_destroy(graph: int) -> None:
+    _lib.prx_graph_destroy(graph)
 
 
 # ---------------------------------------------------------------- autotune

@@ -162,3 +162,28 @@ def test_plain_plan_is_one_pass_per_rotation():
     assert info["passes"] == info["plain_passes"] == 30 and info["kernel_rotations"] == 30
     P.prx_plan_destroy(pl)
     P.prx_sched_destroy(s)
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    assert P.prx_autotune_lookup(7, P.PRX_C128) is None
+    src = tmp_path / "tune.json"
+    src.write_text('{\n  "gfx950/27/c64": {"tile_qubits": 12, "chunk_rank": 5, "max_fuse": 128, '
+                   '"span_max": 3, "max_virtual": 2, "renorm_every": 1, "commuting": 0}\n}\n')
+    P.prx_autotune_load(str(src))
+    got = P.prx_autotune_lookup(27, P.PRX_C64)
+    assert got["tile_qubits"] == 12 and got["chunk_rank"] == 5 and got["max_fuse"] == 128
+    assert got["span_max"] == 3 and got["max_virtual"] == 2
+    out = tmp_path / "out.json"
+    P.prx_autotune_save(str(out))
+    P.prx_autotune_load(str(out))
+    assert P.prx_autotune_lookup(27, P.PRX_C64) == got
+    # AUTO plans pick the cached setting up
+    x, z, phi = synth.random_pauli_rotations(27, 10, 1)
+    s = P.prx_sched_from_rotations(27, x, z, phi)
+    pl = P.prx_plan_create(s, 27, P.PRX_C64, 0, 10, P.PRX_AUTO)
+    info = P.prx_plan_get_info(pl)
+    assert info["tile_qubits"] == 12 and info["chunk_rank"] == 5
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+    with pytest.raises(P.PrxError):
+        P.prx_autotune_load(str(tmp_path / "missing.json"))
