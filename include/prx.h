@@ -287,10 +287,10 @@ typedef struct prx_graph prx_graph;
 
 /* Plans S independent runs: sample s applies sched[s] to its own state
  * (2^n[s] amplitudes of dtype) and reports <basis_idx[s]|psi_s>.  Each
- * sample's schedule is segmented into span passes of a fixed rank, and all
- * samples run in one persistent kernel that pulls (sample, pass, slice) work
- * items from a queue in pass-round order; a per-sample completion counter
- * orders the passes of each sample.  Host only; no device calls.  INVALID if
+ * sample's schedule is segmented into span passes of a fixed rank; round p
+ * applies pass p of every sample that has one, as one grid-stride kernel over
+ * that round's (sample, slice) items, so all samples share every launch and
+ * no workgroup waits on another.  Host only; no device calls.  INVALID if
  * S = 0, an n[s] is outside [6, 34], sched[s]->n != n[s], or basis_idx[s] >=
  * 2^n[s]. */
 prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sched,
@@ -301,14 +301,13 @@ size_t prx_batch_workspace_bytes(const prx_batch *b);
  * `ws`; waits for the copies. */
 prx_status prx_batch_upload(prx_batch *b, void *const *psi, void *ws, size_t ws_bytes,
                             void *stream);
-/* Enqueues, on `stream`, three kernels and nothing else: a reset of the
- * queue and counters, the persistent kernel, and the overlap read-out into
- * overlaps_dev (device array of 2*S doubles, (re, im) per sample).  It can
- * therefore be replayed and captured in a graph. */
+/* Enqueues, on `stream`, kernels only: one per round (the largest pass
+ * count among the samples) and the overlap read-out into overlaps_dev
+ * (device array of 2*S doubles, (re, im) per sample).  It can therefore be
+ * replayed and captured in one graph (prx_batch_graph). */
 prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
                              double *overlaps_dev, void *stream);
-/* Waits for the stream and reports PRX_ERR_HIP if the persistent kernel gave
- * up on a dependency wait (a bounded spin; not expected to trigger). */
+/* Waits for the stream and reports any pending HIP error. */
 prx_status prx_batch_check(const prx_batch *b, const void *ws, void *stream);
 void prx_batch_destroy(prx_batch *b);
 

@@ -1,21 +1,13 @@
-// Batched persistent execution of many independent samples (qDRIFT or
-// partially randomised draws, circuits of uneven qubit counts).
+// Batched execution of many independent samples (qDRIFT or partially
+// randomised draws, circuits of uneven qubit counts).
 //
 // Each sample's schedule is planned into span passes of fixed rank M (the
 // basis padded with unused high directions), so every pass of a sample has
 // the same 2^(n-M) cosets, split into Q slices of at most kSliceCosets.
-// Work items (sample, pass, slice) are handed out from one atomic counter in
-// round order: all samples' pass-0 slices, then all pass-1 slices, ...  An
-// item of pass p waits until its sample's completion counter reaches p*Q.
-// Every item a workgroup waits for was claimed earlier by a workgroup that
-// is already running, so the waits end without any assumption on how many
-// workgroups are resident; a bounded spin marks the batch failed instead of
-// hanging if that reasoning were ever violated.
-//
-// Cross-workgroup visibility of the state (eight XCDs, each with its own
-// L2): the finishing workgroup fences its stores at agent scope before a
-// release increment; the waiting workgroup acquires at agent scope before
-// reading.
+// Round p applies pass p of every sample that has one: a single grid-stride
+// kernel over that round's (sample, slice) items.  Kernel boundaries order
+// the rounds, so no workgroup ever waits on another; the whole sequence of
+// round kernels is enqueued back to back (and can be captured as one graph).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -29,7 +21,6 @@ namespace prx {
 
 static constexpr int kBatchRank = 4;
 static constexpr uint64_t kSliceCosets = 8192;
-static constexpr uint32_t kSpinLimit = 1u << 26;
 
 struct BSample {
     uint64_t psi;       // device address of the state
@@ -51,115 +42,52 @@ struct BatchArgs {
     const BSample *samples;
     const BPass *passes;
     const void *rots;
-    const uint64_t *round_start;  // rounds + 1 entries
     const uint64_t *prefixQ;      // S + 1 entries over the pass-count-sorted samples
     const uint32_t *order;        // sorted position -> sample
-    uint32_t rounds;
-    uint64_t total_items;
-    uint32_t *done;               // per sample
-    unsigned long long *next;     // queue head
-    uint32_t *err;
 };
 
+// Round p: items j in [0, prefixQ[active]) over the first `active` sorted
+// samples; item j is slice j - prefixQ[k] of sorted sample k.
 template <typename T>
-__global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
+__global__ void __launch_bounds__(256) k_batch_round(BatchArgs a, uint32_t p, uint32_t active,
+                                                     uint64_t items) {
     constexpr int M = kBatchRank;
-    __shared__ unsigned long long sh_item;
-    __shared__ uint32_t sh_s, sh_ok;
-    __shared__ uint64_t sh_q;
-    __shared__ uint32_t sh_p;
-    for (;;) {
-        if (threadIdx.x == 0) sh_item = atomicAdd(a.next, 1ull);
-        __syncthreads();
-        const uint64_t item = sh_item;
-        if (item >= a.total_items) break;
-        if (threadIdx.x == 0) {
-            // round: last p with round_start[p] <= item
-            uint32_t lo = 0, hi = a.rounds;  // answer in [lo, hi)
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (a.round_start[mid] <= item) lo = mid; else hi = mid;
-            }
-            const uint32_t p = lo;
-            const uint64_t j = item - a.round_start[p];
-            // sorted sample position: last k with prefixQ[k] <= j (prefixQ is
-            // strictly increasing and padded with ~0 to a power of two + 1)
-            uint32_t l = 0, h = 1;
-            while (a.prefixQ[h] <= j) {
-                l = h;
-                h <<= 1;
-            }
-            while (h - l > 1) {
-                const uint32_t mid = (l + h) >> 1;
-                if (a.prefixQ[mid] <= j) l = mid; else h = mid;
-            }
-            const uint32_t s = a.order[l];
-            sh_s = s;
-            sh_p = p;
-            sh_q = j - a.prefixQ[l];
-            // wait for the sample's previous pass
-            const uint32_t need = p * a.samples[s].Q;
-            uint32_t ok = 1, spins = 0;
-            while (__hip_atomic_load(&a.done[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit) {
-                    atomicOr(a.err, 1u);
-                    ok = 0;
-                    break;
-                }
-            }
-            sh_ok = ok;
+    for (uint64_t j = blockIdx.x; j < items; j += gridDim.x) {
+        // last k < active with prefixQ[k] <= j (uniform across the block)
+        uint32_t lo = 0, hi = active;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.prefixQ[mid] <= j) lo = mid; else hi = mid;
         }
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // fresh view of the state per wave
-        const uint32_t s = __builtin_amdgcn_readfirstlane(sh_s);
-        const uint32_t pidx = __builtin_amdgcn_readfirstlane(sh_p);
-        const uint64_t q = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(sh_q >> 32)) << 32) |
-                           __builtin_amdgcn_readfirstlane((uint32_t)sh_q);
-        const uint32_t ok = __builtin_amdgcn_readfirstlane(sh_ok);
+        const uint32_t s = a.order[lo];
+        const uint64_t q = j - a.prefixQ[lo];
         const BSample smp = a.samples[s];
-        const BPass ps = a.passes[smp.pass_begin + pidx];
-        if (ok) {
-            Cx<T> *psi = reinterpret_cast<Cx<T> *>(smp.psi);
-            const RotRec<T> *rots = reinterpret_cast<const RotRec<T> *>(a.rots) + ps.rot_begin;
-            uint64_t X[1 << M];
-            X[0] = 0;
+        const BPass ps = a.passes[smp.pass_begin + p];
+        Cx<T> *psi = reinterpret_cast<Cx<T> *>(smp.psi);
+        const RotRec<T> *rots = reinterpret_cast<const RotRec<T> *>(a.rots) + ps.rot_begin;
+        uint64_t X[1 << M];
+        X[0] = 0;
 #pragma unroll
-            for (int v = 1; v < (1 << M); ++v) X[v] = X[v & (v - 1)] ^ ps.basis[__builtin_ctz(v)];
-            const T sc = (T)ps.scale;
-            const uint64_t c0 = q * kSliceCosets;
-            const uint64_t c1 = min(c0 + kSliceCosets, smp.ncos);
-            for (uint64_t c = c0 + threadIdx.x; c < c1; c += 256) {
-                uint64_t k0 = c;
+        for (int v = 1; v < (1 << M); ++v) X[v] = X[v & (v - 1)] ^ ps.basis[__builtin_ctz(v)];
+        const T sc = (T)ps.scale;
+        const uint64_t c0 = q * kSliceCosets;
+        const uint64_t c1 = min(c0 + kSliceCosets, smp.ncos);
+        for (uint64_t c = c0 + threadIdx.x; c < c1; c += 256) {
+            uint64_t k0 = c;
 #pragma unroll
-                for (int i = 0; i < M; ++i) k0 = insert_zero64(k0, ps.pivot[i]);
-                Cx<T> amp[1 << M];
+            for (int i = 0; i < M; ++i) k0 = insert_zero64(k0, ps.pivot[i]);
+            Cx<T> amp[1 << M];
 #pragma unroll
-                for (int v = 0; v < (1 << M); ++v) amp[v] = psi[k0 ^ X[v]];
-                apply_rots<T, M>(amp, k0, 0, rots, ps.rot_count);
+            for (int v = 0; v < (1 << M); ++v) amp[v] = psi[k0 ^ X[v]];
+            apply_rots<T, M>(amp, k0, 0, rots, ps.rot_count);
 #pragma unroll
-                for (int v = 0; v < (1 << M); ++v) {
-                    Cx<T> o;
-                    o.re = amp[v].re * sc;
-                    o.im = amp[v].im * sc;
-                    psi[k0 ^ X[v]] = o;
-                }
+            for (int v = 0; v < (1 << M); ++v) {
+                Cx<T> o;
+                o.re = amp[v].re * sc;
+                o.im = amp[v].im * sc;
+                psi[k0 ^ X[v]] = o;
             }
         }
-        __threadfence();  // release this wave's stores at agent scope
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&a.done[s], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-__global__ void k_batch_reset(uint32_t *done, uint32_t S, unsigned long long *next,
-                              uint32_t *err) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < S) done[i] = 0;
-    if (i == 0) {
-        *next = 0;
-        *err = 0;
     }
 }
 
@@ -183,13 +111,14 @@ struct prx_batch {
     std::vector<prx::BSample> samples;
     std::vector<prx::BPass> passes;
     std::vector<unsigned char> rots;
-    std::vector<uint64_t> round_start, prefixQ;
+    std::vector<uint64_t> prefixQ;
     std::vector<uint32_t> order;
+    std::vector<uint32_t> round_active;  // samples with a pass in round p
     uint64_t total_items = 0;
     uint32_t rounds = 0;
     // workspace layout
-    size_t off_samples = 0, off_passes = 0, off_rots = 0, off_round = 0, off_prefix = 0,
-           off_order = 0, off_done = 0, off_next = 0, off_err = 0, total = 0;
+    size_t off_samples = 0, off_passes = 0, off_rots = 0, off_prefix = 0, off_order = 0,
+           total = 0;
 };
 
 struct prx_graph {
@@ -269,28 +198,19 @@ prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sche
         for (size_t k = 0; k < S; ++k)
             b->prefixQ[k + 1] = b->prefixQ[k] + b->samples[b->order[k]].Q;
         b->rounds = b->samples[b->order[0]].pass_count;
-        b->round_start.assign((size_t)b->rounds + 1, 0);
+        b->round_active.assign(b->rounds, 0);
         size_t active = S;
         for (uint32_t p = 0; p < b->rounds; ++p) {
             while (active > 0 && b->samples[b->order[active - 1]].pass_count <= p) --active;
-            b->round_start[p + 1] = b->round_start[p] + b->prefixQ[active];
+            b->round_active[p] = (uint32_t)active;
+            b->total_items += b->prefixQ[active];
         }
-        b->total_items = b->round_start[b->rounds];
-        // a sentinel after the last prefix keeps the doubling search in range
-        const size_t pq = b->prefixQ.size();
-        size_t cap = 1;
-        while (cap < pq) cap <<= 1;
-        b->prefixQ.resize(cap + 1, ~0ull);
         size_t o = 0;
         b->off_samples = o; o = al256(o + S * sizeof(BSample));
         b->off_passes = o;  o = al256(o + b->passes.size() * sizeof(BPass));
         b->off_rots = o;    o = al256(o + b->rots.size());
-        b->off_round = o;   o = al256(o + b->round_start.size() * sizeof(uint64_t));
         b->off_prefix = o;  o = al256(o + b->prefixQ.size() * sizeof(uint64_t));
         b->off_order = o;   o = al256(o + S * sizeof(uint32_t));
-        b->off_done = o;    o = al256(o + S * sizeof(uint32_t));
-        b->off_next = o;    o = al256(o + sizeof(unsigned long long));
-        b->off_err = o;     o = al256(o + sizeof(uint32_t));
         b->total = o;
     } catch (const std::bad_alloc &) {
         delete b;
@@ -321,8 +241,6 @@ prx_status prx_batch_upload(prx_batch *b, void *const *psi, void *ws, size_t ws_
     if (!b->rots.empty())
         PRX_HIP(hipMemcpyAsync(w + b->off_rots, b->rots.data(), b->rots.size(),
                                hipMemcpyHostToDevice, st));
-    PRX_HIP(hipMemcpyAsync(w + b->off_round, b->round_start.data(),
-                           b->round_start.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     PRX_HIP(hipMemcpyAsync(w + b->off_prefix, b->prefixQ.data(),
                            b->prefixQ.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     PRX_HIP(hipMemcpyAsync(w + b->off_order, b->order.data(), b->S * sizeof(uint32_t),
@@ -341,27 +259,25 @@ prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
     a.samples = (const BSample *)(w + b->off_samples);
     a.passes = (const BPass *)(w + b->off_passes);
     a.rots = w + b->off_rots;
-    a.round_start = (const uint64_t *)(w + b->off_round);
     a.prefixQ = (const uint64_t *)(w + b->off_prefix);
     a.order = (const uint32_t *)(w + b->off_order);
-    a.rounds = b->rounds;
-    a.total_items = b->total_items;
-    a.done = (uint32_t *)(w + b->off_done);
-    a.next = (unsigned long long *)(w + b->off_next);
-    a.err = (uint32_t *)(w + b->off_err);
-    const unsigned rb = (unsigned)((b->S + 255) / 256);
-    hipLaunchKernelGGL(k_batch_reset, dim3(rb), dim3(256), 0, st, a.done, (uint32_t)b->S, a.next,
-                       a.err);
-    PRX_HIP(hipGetLastError());
     int dev = 0, cus = 256;
     PRX_HIP(hipGetDevice(&dev));
     PRX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const unsigned grid = (unsigned)std::max(1, cus) * 4u;
-    if (b->dtype == PRX_C64)
-        hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(256), 0, st, a);
-    PRX_HIP(hipGetLastError());
+    const uint64_t cap = (uint64_t)std::max(1, cus) * 8u;
+    for (uint32_t p = 0; p < b->rounds; ++p) {
+        const uint32_t active = b->round_active[p];
+        const uint64_t items = b->prefixQ[active];
+        const unsigned grid = (unsigned)std::min<uint64_t>(items, cap);
+        if (b->dtype == PRX_C64)
+            hipLaunchKernelGGL(k_batch_round<float>, dim3(grid), dim3(256), 0, st, a, p, active,
+                               items);
+        else
+            hipLaunchKernelGGL(k_batch_round<double>, dim3(grid), dim3(256), 0, st, a, p, active,
+                               items);
+        PRX_HIP(hipGetLastError());
+    }
+    const unsigned rb = (unsigned)((b->S + 255) / 256);
     if (b->dtype == PRX_C64)
         hipLaunchKernelGGL(k_batch_overlaps<float>, dim3(rb), dim3(256), 0, st, a.samples,
                            (uint32_t)b->S, overlaps_dev);
@@ -374,12 +290,8 @@ prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
 
 prx_status prx_batch_check(const prx_batch *b, const void *ws, void *stream) {
     if (!b || !ws) return fail(PRX_ERR_INVALID, "null pointer");
-    uint32_t err = 0;
-    hipStream_t st = (hipStream_t)stream;
-    PRX_HIP(hipMemcpyAsync(&err, (const char *)ws + b->off_err, sizeof(err),
-                           hipMemcpyDeviceToHost, st));
-    PRX_HIP(hipStreamSynchronize(st));
-    if (err) return fail(PRX_ERR_HIP, "batched kernel gave up waiting on a pass dependency");
+    PRX_HIP(hipStreamSynchronize((hipStream_t)stream));
+    PRX_HIP(hipGetLastError());
     return PRX_OK;
 }
 

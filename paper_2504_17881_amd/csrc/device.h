@@ -108,15 +108,14 @@ __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], uint64_t k0, ui
         const uint32_t slot = rec.info & 15u;
         const bool imag = (rec.info >> 4) & 1u;
         const uint32_t zeta = (rec.info >> 8) & 0xffu;
-        switch (slot) {
-        case 0: rot_slot_any<T, M, 0>(amp, g, zeta, imag); break;
-        case 1: if constexpr (M > 1) rot_slot_any<T, M, 1>(amp, g, zeta, imag); break;
-        case 2: if constexpr (M > 2) rot_slot_any<T, M, 2>(amp, g, zeta, imag); break;
-        case 3: if constexpr (M > 3) rot_slot_any<T, M, 3>(amp, g, zeta, imag); break;
-        case 4: if constexpr (M > 4) rot_slot_any<T, M, 4>(amp, g, zeta, imag); break;
-        case 5: if constexpr (M > 5) rot_slot_any<T, M, 5>(amp, g, zeta, imag); break;
-        default: rot_diag<T, M>(amp, g, zeta); break;
-        }
+        // one uniform branch per slot, each updating amp in place
+        if (slot == 0) rot_slot_any<T, M, 0>(amp, g, zeta, imag);
+        if constexpr (M > 1) if (slot == 1) rot_slot_any<T, M, 1>(amp, g, zeta, imag);
+        if constexpr (M > 2) if (slot == 2) rot_slot_any<T, M, 2>(amp, g, zeta, imag);
+        if constexpr (M > 3) if (slot == 3) rot_slot_any<T, M, 3>(amp, g, zeta, imag);
+        if constexpr (M > 4) if (slot == 4) rot_slot_any<T, M, 4>(amp, g, zeta, imag);
+        if constexpr (M > 5) if (slot == 5) rot_slot_any<T, M, 5>(amp, g, zeta, imag);
+        if (slot == kSlotDiag) rot_diag<T, M>(amp, g, zeta);
     }
 }
 

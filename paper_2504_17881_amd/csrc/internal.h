@@ -113,7 +113,9 @@ hipError_t launch_span(prx_dtype dt, int m, void *psi, const SpanArgs &a, const 
 hipError_t launch_tile(prx_dtype dt, int B, int m, void *psi, const TileArgs &a,
                        const void *rots, const ChunkRec *chunks, const double *renorm_in,
                        double *norm_out, hipStream_t s, unsigned *blocks_out);
-// partial sums -> 1/sqrt(sum) into *scale_out (single block, fixed shape)
+// partial sums -> 1/sqrt(sum) into scale_out[0]; scale_out[1 .. kRenormStage]
+// is stage-1 scratch (two fixed-shape kernels, deterministic)
+static constexpr unsigned kRenormStage = 128;
 hipError_t launch_renorm_finish(const double *partials, unsigned count, double *scale_out,
                                 hipStream_t s);
 unsigned span_blocks(int n, int m);

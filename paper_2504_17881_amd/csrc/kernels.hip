@@ -298,13 +298,27 @@ __global__ void __launch_bounds__(256) k_finish_pairs(const double *__restrict__
     }
 }
 
-// Sums `count` norm partials and writes 1/sqrt(sum).
-__global__ void __launch_bounds__(256) k_renorm_finish(const double *__restrict__ part,
+// Norm hand-off, stage 1: block b sums its contiguous share of the
+// `count` partials into stage[b] (fixed shape, deterministic).
+__global__ void __launch_bounds__(256) k_renorm_stage1(const double *__restrict__ part,
+                                                       unsigned count, double *__restrict__ stage) {
+    __shared__ double sh[256];
+    const unsigned per = (count + gridDim.x - 1) / gridDim.x;
+    const unsigned lo = blockIdx.x * per;
+    const unsigned hi = min(count, lo + per);
+    Neu acc;
+    for (unsigned i = lo + threadIdx.x; i < hi; i += 256u) acc.add(part[i]);
+    const double s = tree256(acc.value(), sh);
+    if (threadIdx.x == 0) stage[blockIdx.x] = s;
+}
+
+// Stage 2: sums the stage-1 values and writes 1/sqrt(sum).
+__global__ void __launch_bounds__(256) k_renorm_finish(const double *__restrict__ stage,
                                                        unsigned count,
                                                        double *__restrict__ scale_out) {
     __shared__ double sh[256];
     Neu acc;
-    for (unsigned i = threadIdx.x; i < count; i += 256u) acc.add(part[i]);
+    for (unsigned i = threadIdx.x; i < count; i += 256u) acc.add(stage[i]);
     const double s = tree256(acc.value(), sh);
     if (threadIdx.x == 0) scale_out[0] = 1.0 / sqrt(s);
 }
@@ -429,7 +443,11 @@ hipError_t launch_tile(prx_dtype dt, int B, int m, void *psi, const TileArgs &a,
 
 hipError_t launch_renorm_finish(const double *partials, unsigned count, double *scale_out,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_renorm_finish, dim3(1), dim3(256), 0, s, partials, count, scale_out);
+    // scale_out[1 .. kRenormStage] holds the stage-1 sums
+    double *stage = scale_out + 1;
+    const unsigned g = count < 4096u ? 1u : kRenormStage;
+    hipLaunchKernelGGL(k_renorm_stage1, dim3(g), dim3(256), 0, s, partials, count, stage);
+    hipLaunchKernelGGL(k_renorm_finish, dim3(1), dim3(256), 0, s, stage, g, scale_out);
     return hipGetLastError();
 }
 

@@ -194,7 +194,8 @@ struct Builder {
         P.plain_passes++;
     }
 
-    size_t emit_span(size_t p) {
+    size_t emit_span(size_t p, size_t limit = ~(size_t)0) {
+        const size_t stop = std::min(end, limit);
         Gf2 g;
         std::vector<uint64_t> basis;
         size_t j = p;
@@ -202,7 +203,7 @@ struct Builder {
             if (r.x == 0 || std::find(basis.begin(), basis.end(), r.x) != basis.end()) return true;
             return (int)basis.size() < cfg.span_m && !g.contains(r.x);
         };
-        for (; j < end && (int)(j - p) < cfg.max_fuse; ++j) {
+        for (; j < stop && (int)(j - p) < cfg.max_fuse; ++j) {
             if (!fits(R[j]) && !pull_forward(j, fits)) break;
             const uint64_t x = R[j].x;
             if (x && std::find(basis.begin(), basis.end(), x) == basis.end()) {
@@ -253,7 +254,8 @@ struct Builder {
         return j;
     }
 
-    size_t emit_tile(size_t p, int g) {
+    size_t emit_tile(size_t p, int g, size_t limit = ~(size_t)0) {
+        const size_t stop = std::min(end, limit);
         const int b = cfg.B - g;
         const uint64_t low = (b >= 64) ? ~0ull : ((1ull << b) - 1ull);
         Gf2 M;
@@ -262,7 +264,7 @@ struct Builder {
             Gf2 copy = M;
             return tile_fits(r.x, b, copy, g, false);
         };
-        for (; j < end && (int)(j - p) < cfg.max_fuse; ++j) {
+        for (; j < stop && (int)(j - p) < cfg.max_fuse; ++j) {
             if (!fits(R[j]) && !pull_forward(j, fits)) break;
             tile_fits(R[j].x, b, M, g, true);
         }
@@ -376,8 +378,77 @@ struct Builder {
         while (p < end) p = emit_span(p);
     }
 
+    // Longest pass from p: its end, the kind (kSpan or kTile) and tile g.
+    struct Reach {
+        size_t end;
+        int kind, g;
+    };
+    Reach reach_from(size_t p, bool tile_ok) const {
+        Reach r{p + span_len(p, cfg.span_m), kSpan, 0};
+        if (tile_ok) {
+            for (int g = 0; g <= cfg.max_virtual && g <= P.n - cfg.B; ++g) {
+                const size_t e = p + tile_len(p, g);
+                if (e > r.end) r = Reach{e, kTile, g};
+            }
+        }
+        return r;
+    }
+
+    // Emits passes covering exactly [p, q): one pass of kind r when it
+    // reaches q (always, by construction of r), else further passes.
+    void emit_range(size_t p, size_t q, Reach r) {
+        while (p < q) {
+            if (q - p == 1) {
+                emit_plain(p);
+                ++p;
+                continue;
+            }
+            size_t got = r.kind == kTile ? emit_tile(p, r.g, q) : emit_span(p, q);
+            if (got <= p) {
+                emit_plain(p);
+                got = p + 1;
+            }
+            p = got;
+            r = Reach{q, kSpan, 0};
+        }
+    }
+
+    // Minimum number of passes: every pass may end anywhere inside its
+    // longest reach (a prefix of a valid pass is valid), so the next pass
+    // starts at the cut inside the current reach whose own reach is furthest
+    // (the greedy that is optimal for covering a line by jumps).
     void run_fused() {
         const bool tile_ok = P.n >= cfg.B + 1 && tile_supported(P.dtype, cfg.B, cfg.m);
+        if (cfg.commuting) {
+            run_fused_greedy(tile_ok);
+            return;
+        }
+        const size_t b0 = P.begin;
+        std::vector<Reach> reach(end - b0);
+        for (size_t p = b0; p < end; ++p) reach[p - b0] = reach_from(p, tile_ok);
+        size_t p = b0;
+        while (p < end) {
+            const Reach &r = reach[p - b0];
+            if (r.end >= end) {
+                emit_range(p, end, r);
+                break;
+            }
+            size_t cut = r.end, far = reach[r.end - b0].end;
+            for (size_t c = p + 1; c < r.end; ++c) {
+                if (reach[c - b0].end > far) {
+                    far = reach[c - b0].end;
+                    cut = c;
+                }
+            }
+            // a span pass covering [p, cut) when one exists (cheaper than a tile pass)
+            Reach use = r;
+            if (r.kind == kTile && p + span_len(p, cfg.span_m) >= cut) use = Reach{cut, kSpan, 0};
+            emit_range(p, cut, use);
+            p = cut;
+        }
+    }
+
+    void run_fused_greedy(bool tile_ok) {
         size_t p = P.begin;
         while (p < end) {
             const size_t fs = span_len(p, cfg.span_m);
@@ -394,19 +465,15 @@ struct Builder {
             }
             if (ft > fs && ft >= 2) {
                 p = emit_tile(p, gbest);
-            } else if (fs >= 2 || cfg.commuting) {
+            } else {
                 const size_t q = emit_span(p);
                 if (q - p == 1 && P.passes.back().kind == kSpan) {
-                    // a lone rotation: a plain sweep is the same traffic
                     P.passes.pop_back();
                     P.span_passes--;
                     recs.pop_back();
                     emit_plain(p);
                 }
                 p = q;
-            } else {
-                emit_plain(p);
-                ++p;
             }
         }
     }
@@ -545,7 +612,7 @@ static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtyp
         w.part_off = align256(w.chunk_off + w.chunk_bytes);
         w.part_bytes = maxblocks * sizeof(double);
         w.scal_off = align256(w.part_off + w.part_bytes);
-        w.scal_bytes = 64;
+        w.scal_bytes = (1 + kRenormStage) * sizeof(double);
         w.total = align256(w.scal_off + w.scal_bytes);
     } catch (const std::bad_alloc &) {
         delete P;

@@ -125,9 +125,9 @@ def jw_hamiltonian(n: int, L: int, seed: int = 0):
       * endpoint letters X or Y uniformly; interior letters Z;
       * coefficient: a uniform sign times exp(N(mu=-4, sigma=2)).
     A term equal to one already drawn is redrawn at the same weight (up to
-    64 tries) and then at a new weight from the same bucket, so the 60/40
-    bucket split holds even where the low weights run out of distinct
-    strings.  Returns (x uint64[L], z uint64[L], h float64[L]).
+    64 tries) and then at a new weight from the same bucket; only when a
+    bucket has no distinct strings left (small n with large L) is the term
+    drawn from the other bucket.  Returns (x uint64[L], z uint64[L], h float64[L]).
     """
     if n < 2:
         raise ValueError("need n >= 2")
@@ -135,20 +135,28 @@ def jw_hamiltonian(n: int, L: int, seed: int = 0):
     seen = set()
     xs, zs, hs = [], [], []
     big = list(range(5, n + 1))
+    exhausted = {True: False, False: not big}
     while len(xs) < L:
         small_bucket = rng.random() < 0.6 or not big
-        for _ in range(4096):
-            w = int(rng.integers(2, 5)) if small_bucket else int(rng.choice(big))
-            w = min(w, n)
-            got = None
-            for _ in range(64):
-                key = _draw_term(rng, n, w)
-                if key not in seen:
-                    got = key
+        got = None
+        # a bucket whose distinct strings have run out hands over to the other
+        for small in ((True, False) if small_bucket else (False, True)):
+            if exhausted[small]:
+                continue
+            for _ in range(4096):
+                w = int(rng.integers(2, 5)) if small else int(rng.choice(big))
+                w = min(w, n)
+                for _ in range(64):
+                    key = _draw_term(rng, n, w)
+                    if key not in seen:
+                        got = key
+                        break
+                if got is not None:
                     break
             if got is not None:
                 break
-        else:
+            exhausted[small] = True
+        if got is None:
             raise ValueError(f"cannot draw {L} distinct terms on {n} qubits")
         seen.add(got)
         xs.append(got[0])

@@ -187,3 +187,25 @@ def test_autotune_cache_roundtrip(tmp_path):
     P.prx_sched_destroy(s)
     with pytest.raises(P.PrxError):
         P.prx_autotune_load(str(tmp_path / "missing.json"))
+
+
+def test_batch_create_host_checks():
+    ns = [6, 8, 7]
+    hams, scheds = [], []
+    for i, n in enumerate(ns):
+        x, z, h = synth.jw_hamiltonian(n, 30, 1000 + n)
+        H = P.prx_ham_create(n, x, z, h)
+        hams.append(H)
+        scheds.append(P.prx_sched_qdrift(H, 1.0, 40, i))
+    basis = [synth.basis_index(n) for n in ns]
+    b = P.prx_batch_create(ns, scheds, P.PRX_C64, basis)
+    assert P.prx_batch_workspace_bytes(b) > 0
+    P.prx_batch_destroy(b)
+    for bad_n, bad_b in [([6, 8, 5], basis), (ns, [0, 1 << 8, 0]), ([6, 9, 7], basis)]:
+        with pytest.raises(P.PrxError) as e:
+            P.prx_batch_create(bad_n, scheds, P.PRX_C64, bad_b)
+        assert e.value.status == P.PRX_ERR_INVALID
+    for s in scheds:
+        P.prx_sched_destroy(s)
+    for H in hams:
+        P.prx_ham_destroy(H)

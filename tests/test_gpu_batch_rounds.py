@@ -1,0 +1,138 @@
+"""GPU tests of the batched path: one grid-stride kernel per pass round over
+all samples' slices (no cross-workgroup waits), captured as one graph."""
+import math
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import schedules as S
+from oracle import statevector as sv
+from paper_2504_17881_amd import prx as P
+from gpu_util import basis_state, dev, rel_err, to_host, workspace
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+
+
+def _inputs(ns, L, N, t, seed0=0):
+    hams, scheds = {}, []
+    for i, n in enumerate(ns):
+        if n not in hams:
+            x, z, h = synth.jw_hamiltonian(n, L, 1000 + n)
+            hams[n] = (x, z, h, P.prx_ham_create(n, x, z, h))
+        scheds.append(P.prx_sched_qdrift(hams[n][3], t, N, seed0 + i))
+    return hams, scheds
+
+
+def _free(hams, scheds):
+    for s in scheds:
+        P.prx_sched_destroy(s)
+    for v in hams.values():
+        P.prx_ham_destroy(v[3])
+
+
+@pytest.mark.parametrize("dtype", [P.PRX_C128, P.PRX_C64])
+def test_rounds_match_oracle_per_sample(dtype):
+    ns = [6, 9, 12, 7, 14, 10, 8, 13, 11, 6, 15, 9]
+    N = 150
+    hams, scheds = _inputs(ns, 60, N, 1.0)
+    basis = [synth.basis_index(n) for n in ns]
+    psis = [basis_state(n, b, dtype) for n, b in zip(ns, basis)]
+    b = P.prx_batch_create(ns, scheds, dtype, basis)
+    ws = workspace(P.prx_batch_workspace_bytes(b))
+    ovd = torch.zeros(2 * len(ns), dtype=torch.float64, device=dev())
+    P.prx_batch_upload(b, psis, ws)
+    print(f"[rounds dtype={dtype}] launching", flush=True)
+    P.prx_batch_execute(b, ws, ovd)
+    P.prx_batch_check(b, ws)
+    print(f"[rounds dtype={dtype}] done", flush=True)
+    ov = ovd.cpu().numpy()
+    tol = 1e-12 if dtype == P.PRX_C128 else 8 * EPS32 * math.sqrt(N) + 1e-6
+    for i, n in enumerate(ns):
+        x, z, h, _ = hams[n]
+        rx, rz, rp = S.qdrift(x, z, h, 1.0, N, i)
+        psi0 = np.zeros(1 << n, dtype=np.complex128)
+        psi0[basis[i]] = 1
+        ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+        assert rel_err(to_host(psis[i]), ref) <= tol, (i, n)
+        assert abs(complex(ov[2 * i], ov[2 * i + 1]) - ref[basis[i]]) <= max(tol, 1e-12)
+    P.prx_batch_destroy(b)
+    _free(hams, scheds)
+
+
+def test_rounds_one_call_and_graph_replay():
+    dtype = P.PRX_C64
+    ns = [8, 11, 16, 9, 12]
+    hams, scheds = _inputs(ns, 50, 120, 0.7, seed0=40)
+    basis = [synth.basis_index(n) for n in ns]
+    b = P.prx_batch_create(ns, scheds, dtype, basis)
+    need = P.prx_batch_workspace_bytes(b) + 256 + 16 * len(ns)
+    P.prx_batch_destroy(b)
+    psis = [basis_state(n, k, dtype) for n, k in zip(ns, basis)]
+    eager = P.prx_batch_run(psis, ns, scheds, dtype, basis, workspace(need + 256))
+    stream = torch.cuda.Stream()
+    b = P.prx_batch_create(ns, scheds, dtype, basis)
+    ws2 = workspace(P.prx_batch_workspace_bytes(b))
+    ovd = torch.zeros(2 * len(ns), dtype=torch.float64, device=dev())
+    psis2 = [basis_state(n, k, dtype) for n, k in zip(ns, basis)]
+    P.prx_batch_upload(b, psis2, ws2, stream=stream)
+    g = P.prx_batch_graph(b, ws2, ovd, stream)
+    for rep in range(3):
+        for t, k in zip(psis2, basis):
+            t.zero_()
+            t[k] = 1.0
+        torch.cuda.synchronize()
+        P.prx_graph_launch(g, stream)
+        stream.synchronize()
+        ov = ovd.cpu().numpy()
+        assert np.array_equal(ov[0::2] + 1j * ov[1::2], eager), rep
+    P.prx_graph_destroy(g)
+    P.prx_batch_destroy(b)
+    _free(hams, scheds)
+
+
+def test_qdrift_batch_workload_full_size():
+    """The batching workload: 256 qDRIFT samples, n uniform on {16..24}, per-size
+    JW H with L=500, N=2000 draws, t=1, complex64, basis states, one graph
+    launch.  Every sample's norm stays 1 within the FP32 bound; the smallest
+    samples' overlaps match the oracle."""
+    w = synth.WORKLOADS["qdrift_batch"]
+    ns = synth.batch_qubit_counts(w["S"], w["n_lo"], w["n_hi"], w["n_seed"])
+    dtype = P.PRX_C64
+    hams, scheds = _inputs(ns, w["L"], w["N"], w["t"])
+    basis = [synth.basis_index(n) for n in ns]
+    psis = [basis_state(n, k, dtype) for n, k in zip(ns, basis)]
+    b = P.prx_batch_create(ns, scheds, dtype, basis)
+    ws = workspace(P.prx_batch_workspace_bytes(b))
+    ovd = torch.zeros(2 * len(ns), dtype=torch.float64, device=dev())
+    stream = torch.cuda.Stream()
+    P.prx_batch_upload(b, psis, ws, stream=stream)
+    g = P.prx_batch_graph(b, ws, ovd, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.prx_graph_launch(g, stream)
+    stream.synchronize()
+    dt = time.perf_counter() - t0
+    ov = ovd.cpu().numpy()
+    ovc = ov[0::2] + 1j * ov[1::2]
+    print(f"[qdrift batch] S={len(ns)} {dt:.3f} s, {len(ns) / dt:.1f} samples/s, "
+          f"mean overlap {np.mean(ovc):.6f}", flush=True)
+    rws = workspace(P.prx_reduce_workspace_bytes(24))
+    for i, n in enumerate(ns):
+        nn = P.prx_norm2(psis[i], n, dtype, rws)
+        assert abs(nn - 1.0) <= 1e-4, (i, n, nn)
+    for i in [i for i, n in enumerate(ns) if n == min(ns)][:3]:
+        n = ns[i]
+        x, z, h, _ = hams[n]
+        rx, rz, rp = S.qdrift(x, z, h, w["t"], w["N"], i)
+        psi0 = np.zeros(1 << n, dtype=np.complex128)
+        psi0[basis[i]] = 1
+        ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+        assert abs(ovc[i] - ref[basis[i]]) <= 1e-4
+    P.prx_graph_destroy(g)
+    P.prx_batch_destroy(b)
+    _free(hams, scheds)
