@@ -33,6 +33,7 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
+TUNE_CACHE = os.path.join(ROOT, "paper_2504_17881_amd", "tuning", "gfx950.json")
 METRIC = "amplitude-updates/s and %HBM peak at n=32, FP32-fused vs FP64-plain"
 
 
@@ -111,6 +112,12 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--fused-only", action="store_true",
                     help="skip the FP64-plain comparator (profiling runs)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotune cache (JSON) loaded before planning; plans use PRX_AUTO")
+    ap.add_argument("--autotune-save", default=None,
+                    help="run the autotuner on the first --tune-rotations rotations first and "
+                         "save its cache to this path")
+    ap.add_argument("--tune-rotations", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path is a "
@@ -134,8 +141,29 @@ def main() -> int:
     dev = torch.device("cuda:0")
     print(f"[bench] n={n} L={L} rotations={len(sx)}", file=sys.stderr, flush=True)
 
+    # ---------------- planner settings: tuned cache (or a fresh tuning run)
+    tuned = None
+    if args.autotune_save:
+        print("[bench] autotuning", file=sys.stderr, flush=True)
+        R = min(args.tune_rotations, len(sx))
+        sub = P.prx_sched_from_rotations(n, sx[:R], sz[:R], sphi[:R])
+        scratch = torch.zeros(1 << n, dtype=torch.complex64, device=dev)
+        scratch[k0] = 1.0
+        tws = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        tuned, trials = P.prx_autotune(scratch, n, P.PRX_C64, sub, tws)
+        os.makedirs(os.path.dirname(os.path.abspath(args.autotune_save)), exist_ok=True)
+        P.prx_autotune_save(args.autotune_save)
+        print(f"[bench] autotune: {trials} trials, best {tuned}", file=sys.stderr, flush=True)
+        P.prx_sched_destroy(sub)
+        del scratch, tws
+        torch.cuda.empty_cache()
+    elif args.tune_cache and os.path.exists(args.tune_cache):
+        P.prx_autotune_load(args.tune_cache)
+        tuned = P.prx_autotune_lookup(n, P.PRX_C64)
+    kernel = P.PRX_AUTO if tuned else P.PRX_FUSED
+
     # ---------------- fused complex64: one plan per Trotter step (identical steps)
-    plan = P.prx_plan_create(sched, n, P.PRX_C64, 0, L, P.PRX_FUSED)
+    plan = P.prx_plan_create(sched, n, P.PRX_C64, 0, L, kernel)
     info = P.prx_plan_get_info(plan)
     passes = [P.prx_plan_pass(plan, i) for i in range(info["passes"])]
     names = [kernel_symbol(p, "float") for p in passes]
@@ -244,6 +272,7 @@ def main() -> int:
             "passes_per_step": info["passes"], "mean_fuse": info["mean_fuse"],
             "span_passes": info["span_passes"], "tile_passes": info["tile_passes"],
             "plain_passes": info["plain_passes"],
+            "planner": ({k: v for k, v in tuned.items() if v} if tuned else "defaults"),
         },
         "roofline": {
             "bound": "hbm",

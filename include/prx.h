@@ -213,6 +213,7 @@ typedef struct {
     uint64_t vcomb[8];                /* tile: XOR of virtual masks per combination */
     uint32_t tpivot[3];               /* tile: ascending pivot bits in tile-index space */
     double scale;
+    double fscale[6];                 /* span: pending per-slot factors (see prx_rot_info) */
     int norm_out, renorm_in;          /* C64 renormalisation hand-off */
 } prx_pass_info;
 
@@ -221,21 +222,29 @@ typedef struct {
 typedef struct {
     uint32_t basis[6];
     uint32_t pivot[6];
+    double fscale[6];                 /* pending per-slot factors at the chunk's end */
     size_t rot_begin, rot_count;
 } prx_chunk_info;
 
-/* A kernel rotation: (x, z, phi) as applied (a rotation with |cos phi| <
- * 1/2 appears as two half-angle rotations in fused plans), its schedule
- * index, and its record: z in the kernel's frame, the tile-index part
- * zhigh, basis slot (15 = diagonal), whether tau is imaginary, zeta
- * (bit i = parity(basis_i & z)) and the signed magnitude of tau. */
+/* A kernel rotation: (x, z, phi) as applied (fused plans apply a rotation
+ * with |tan phi| > 1/sqrt(2) as k equal pieces), its schedule index, and
+ * its record: z in the kernel's frame, the tile-index part zhigh, basis slot
+ * (15 = diagonal), whether tau = i^{nY+1} tan(phi) is imaginary, zeta (bit
+ * i = parity(basis_i & z)), and the pair-update coefficients.  A pair (a, b)
+ * (b = a's partner, basis bit set) is updated in place as a <- a + u tau_a
+ * s_b b, then b <- b + u tau_b s_a a (u = 1 or i, s the signs); b is then
+ * held divided by kappa = 1 -/+ tau^2, tracked as per-slot factors K
+ * (tau_a = tau K, tau_b = tau / (K kappa), K <- K kappa); the true value of
+ * the element with coset label v is its stored value times the product of
+ * fscale[i] over the bits i set in v. */
 typedef struct {
     uint64_t x, z;
     double phi;
     size_t source;
     uint64_t zframe, zhigh;
     uint32_t slot, imag, zeta;
-    double tau;
+    double tau;      /* tau_a (for x = 0: tan(phi)) */
+    double tau_b;
 } prx_rot_info;
 
 prx_status prx_plan_pass(const prx_plan *plan, size_t i, prx_pass_info *out);

@@ -4,7 +4,7 @@
 
 Every source is compiled with hipcc for gfx950 into ``_build/`` and linked
 into ``paper_2504_17881_amd/lib/libprx.so``.  Packed FP32 instructions are
-disabled for device code.
+disabled for device code; wave-uniform branches are left unstructurized.
 """
 from __future__ import annotations
 
@@ -27,6 +27,9 @@ SOURCES = ["sched.cpp", "plan.cpp", "kernels.hip", "batch.hip", "tune.cpp"]
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep uniform (scalar) branches unstructurized: the rotation loop's slot
+    # dispatch then updates the amplitudes in place with no register copies
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]

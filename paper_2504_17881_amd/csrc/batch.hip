@@ -36,6 +36,7 @@ struct BPass {
     uint32_t pivot[kBatchRank];
     uint32_t rot_begin, rot_count;
     double scale;
+    double fscale[kBatchRank];
 };
 
 struct BatchArgs {
@@ -69,7 +70,11 @@ __global__ void __launch_bounds__(256) k_batch_round(BatchArgs a, uint32_t p, ui
         X[0] = 0;
 #pragma unroll
         for (int v = 1; v < (1 << M); ++v) X[v] = X[v & (v - 1)] ^ ps.basis[__builtin_ctz(v)];
-        const T sc = (T)ps.scale;
+        double F[1 << M];
+        pending_factors<M>(F, ps.fscale);
+        T sc[1 << M];
+#pragma unroll
+        for (int v = 0; v < (1 << M); ++v) sc[v] = (T)(ps.scale * F[v]);
         const uint64_t c0 = q * kSliceCosets;
         const uint64_t c1 = min(c0 + kSliceCosets, smp.ncos);
         for (uint64_t c = c0 + threadIdx.x; c < c1; c += 256) {
@@ -83,8 +88,8 @@ __global__ void __launch_bounds__(256) k_batch_round(BatchArgs a, uint32_t p, ui
 #pragma unroll
             for (int v = 0; v < (1 << M); ++v) {
                 Cx<T> o;
-                o.re = amp[v].re * sc;
-                o.im = amp[v].im * sc;
+                o.re = amp[v].re * sc[v];
+                o.im = amp[v].im * sc[v];
                 psi[k0 ^ X[v]] = o;
             }
         }
@@ -181,6 +186,7 @@ prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sche
                 bp.rot_begin = rot_base + (uint32_t)ps.r0;
                 bp.rot_count = (uint32_t)(ps.r1 - ps.r0);
                 bp.scale = ps.scale;
+                for (int i = 0; i < kBatchRank; ++i) bp.fscale[i] = ps.fscale[i];
                 b->passes.push_back(bp);
             }
             b->rots.insert(b->rots.end(), P->rot_table.begin(), P->rot_table.end());

@@ -51,71 +51,139 @@ __device__ __forceinline__ double flip(double v, uint32_t p) {
 // sigma0 XOR parity(v & zeta).  A rotation whose x is basis direction I
 // pairs v with v | (1 << I).
 
+// In-place update of one pair (a, b) (see RotRec):
+//     a <- a + ga * b,   then  b <- b + gb * a       (real tau)
+//     a <- a + i ga * b, then  b <- b + i gb * a     (imaginary tau)
+// Tied asm operands keep a and b in their registers, so the rotation loop
+// needs no register copies whichever slot it takes.
+__device__ __forceinline__ void pair_real(Cx<float> &a, Cx<float> &b, float ga, float gb) {
+    asm("v_fma_f32 %0, %4, %2, %0\n\t"
+        "v_fma_f32 %1, %4, %3, %1\n\t"
+        "v_fma_f32 %2, %5, %0, %2\n\t"
+        "v_fma_f32 %3, %5, %1, %3"
+        : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
+        : "v"(ga), "v"(gb));
+}
+__device__ __forceinline__ void pair_imag(Cx<float> &a, Cx<float> &b, float ga, float gb) {
+    asm("v_fma_f32 %0, -%4, %3, %0\n\t"
+        "v_fma_f32 %1, %4, %2, %1\n\t"
+        "v_fma_f32 %2, -%5, %1, %2\n\t"
+        "v_fma_f32 %3, %5, %0, %3"
+        : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
+        : "v"(ga), "v"(gb));
+}
+// a <- a (1 + i g)
+__device__ __forceinline__ void self_imag(Cx<float> &a, float g) {
+    float t;
+    asm("v_mov_b32 %2, %0\n\t"
+        "v_fma_f32 %0, -%3, %1, %0\n\t"
+        "v_fma_f32 %1, %3, %2, %1"
+        : "+v"(a.re), "+v"(a.im), "=&v"(t)
+        : "v"(g));
+}
+__device__ __forceinline__ void pair_real(Cx<double> &a, Cx<double> &b, double ga, double gb) {
+    asm("v_fma_f64 %0, %4, %2, %0\n\t"
+        "v_fma_f64 %1, %4, %3, %1\n\t"
+        "v_fma_f64 %2, %5, %0, %2\n\t"
+        "v_fma_f64 %3, %5, %1, %3"
+        : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
+        : "v"(ga), "v"(gb));
+}
+__device__ __forceinline__ void pair_imag(Cx<double> &a, Cx<double> &b, double ga, double gb) {
+    asm("v_fma_f64 %0, -%4, %3, %0\n\t"
+        "v_fma_f64 %1, %4, %2, %1\n\t"
+        "v_fma_f64 %2, -%5, %1, %2\n\t"
+        "v_fma_f64 %3, %5, %0, %3"
+        : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
+        : "v"(ga), "v"(gb));
+}
+__device__ __forceinline__ void self_imag(Cx<double> &a, double g) {
+    double t;
+    asm("v_mov_b64 %2, %0\n\t"
+        "v_fma_f64 %0, -%3, %1, %0\n\t"
+        "v_fma_f64 %1, %3, %2, %1"
+        : "+v"(a.re), "+v"(a.im), "=&v"(t)
+        : "v"(g));
+}
+
+// Sign masks S[v] = parity(v & zeta) << 31 for all coset labels v, built
+// incrementally (one XOR per label).
+template <int M>
+__device__ __forceinline__ void sign_masks(uint32_t (&S)[1 << M], uint32_t zeta) {
+    S[0] = 0;
+#pragma unroll
+    for (int v = 1; v < (1 << M); ++v)
+        S[v] = S[v & (v - 1)] ^ (((zeta >> __builtin_ctz(v)) & 1u) << 31);
+}
+
+__device__ __forceinline__ float flipm(float v, uint32_t m) { return __uint_as_float(__float_as_uint(v) ^ m); }
+__device__ __forceinline__ double flipm(double v, uint32_t m) {
+    return __longlong_as_double(__double_as_longlong(v) ^ ((uint64_t)m << 32));
+}
+
 template <typename T, int M, int I, bool IMAG>
-__device__ __forceinline__ void rot_slot(Cx<T> (&amp)[1 << M], T g, uint32_t zeta) {
+__device__ __forceinline__ void rot_slot(Cx<T> (&amp)[1 << M], T ga, T gb, uint32_t zeta) {
+    uint32_t S[1 << M];
+    sign_masks<M>(S, zeta);
 #pragma unroll
     for (int v = 0; v < (1 << M); ++v) {
         if (v & (1 << I)) continue;
         const int w = v | (1 << I);
-        const T gw = flip(g, (uint32_t)__builtin_popcount((uint32_t)w & zeta) & 1u);
-        const T gv = flip(g, (uint32_t)__builtin_popcount((uint32_t)v & zeta) & 1u);
-        const Cx<T> av = amp[v], aw = amp[w];
-        if (IMAG) {
-            amp[v].re = fmat(-gw, aw.im, av.re);
-            amp[v].im = fmat(gw, aw.re, av.im);
-            amp[w].re = fmat(-gv, av.im, aw.re);
-            amp[w].im = fmat(gv, av.re, aw.im);
-        } else {
-            amp[v].re = fmat(gw, aw.re, av.re);
-            amp[v].im = fmat(gw, aw.im, av.im);
-            amp[w].re = fmat(gv, av.re, aw.re);
-            amp[w].im = fmat(gv, av.im, aw.im);
-        }
+        if (IMAG)
+            pair_imag(amp[v], amp[w], flipm(ga, S[w]), flipm(gb, S[v]));
+        else
+            pair_real(amp[v], amp[w], flipm(ga, S[w]), flipm(gb, S[v]));
     }
 }
 
-// x = 0: new = psi (1 + i tau' sigma), tau' = tan(phi) (tau is imaginary).
+// x = 0: new = psi (1 + i tan(phi) sigma) (tau is imaginary).
 template <typename T, int M>
 __device__ __forceinline__ void rot_diag(Cx<T> (&amp)[1 << M], T g, uint32_t zeta) {
+    uint32_t S[1 << M];
+    sign_masks<M>(S, zeta);
 #pragma unroll
-    for (int v = 0; v < (1 << M); ++v) {
-        const T gv = flip(g, (uint32_t)__builtin_popcount((uint32_t)v & zeta) & 1u);
-        const Cx<T> av = amp[v];
-        amp[v].re = fmat(-gv, av.im, av.re);
-        amp[v].im = fmat(gv, av.re, av.im);
-    }
+    for (int v = 0; v < (1 << M); ++v) self_imag(amp[v], flipm(g, S[v]));
+}
+
+// Element v's pending factor: the product of K over the slots set in v.
+template <int M>
+__device__ __forceinline__ void pending_factors(double (&F)[1 << M], const double *K) {
+    F[0] = 1.0;
+#pragma unroll
+    for (int v = 1; v < (1 << M); ++v) F[v] = F[v & (v - 1)] * K[__builtin_ctz(v)];
 }
 
 template <typename T, int M, int I>
-__device__ __forceinline__ void rot_slot_any(Cx<T> (&amp)[1 << M], T g, uint32_t zeta,
+__device__ __forceinline__ void rot_slot_any(Cx<T> (&amp)[1 << M], T ga, T gb, uint32_t zeta,
                                              bool imag) {
     if (imag)
-        rot_slot<T, M, I, true>(amp, g, zeta);
+        rot_slot<T, M, I, true>(amp, ga, gb, zeta);
     else
-        rot_slot<T, M, I, false>(amp, g, zeta);
+        rot_slot<T, M, I, false>(amp, ga, gb, zeta);
 }
 
 // Applies rotations [0, count) of `rots` to the thread's coset.
-// k0: coset representative in the frame of rec.z; tsign_base: the tile
-// index whose parity with rec.zhigh adds to the sign (0 for span passes).
+// k0: coset representative in the frame of rec.z; tbase: the tile index
+// whose parity with rec.zhigh adds to the sign (0 for span passes).
 template <typename T, int M>
 __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], uint64_t k0, uint64_t tbase,
                                            const RotRec<T> *__restrict__ rots, uint32_t count) {
     for (uint32_t r = 0; r < count; ++r) {
         const RotRec<T> rec = rots[r];
         const uint32_t s0 = parity64(k0 & rec.z) ^ parity64(tbase & rec.zhigh);
-        const T g = pin(flip(rec.tau, s0));
+        const T ga = pin(flip(rec.tau_a, s0));
+        const T gb = pin(flip(rec.tau_b, s0));
         const uint32_t slot = rec.info & 15u;
         const bool imag = (rec.info >> 4) & 1u;
         const uint32_t zeta = (rec.info >> 8) & 0xffu;
         // one uniform branch per slot, each updating amp in place
-        if (slot == 0) rot_slot_any<T, M, 0>(amp, g, zeta, imag);
-        if constexpr (M > 1) if (slot == 1) rot_slot_any<T, M, 1>(amp, g, zeta, imag);
-        if constexpr (M > 2) if (slot == 2) rot_slot_any<T, M, 2>(amp, g, zeta, imag);
-        if constexpr (M > 3) if (slot == 3) rot_slot_any<T, M, 3>(amp, g, zeta, imag);
-        if constexpr (M > 4) if (slot == 4) rot_slot_any<T, M, 4>(amp, g, zeta, imag);
-        if constexpr (M > 5) if (slot == 5) rot_slot_any<T, M, 5>(amp, g, zeta, imag);
-        if (slot == kSlotDiag) rot_diag<T, M>(amp, g, zeta);
+        if (slot == 0) rot_slot_any<T, M, 0>(amp, ga, gb, zeta, imag);
+        if constexpr (M > 1) if (slot == 1) rot_slot_any<T, M, 1>(amp, ga, gb, zeta, imag);
+        if constexpr (M > 2) if (slot == 2) rot_slot_any<T, M, 2>(amp, ga, gb, zeta, imag);
+        if constexpr (M > 3) if (slot == 3) rot_slot_any<T, M, 3>(amp, ga, gb, zeta, imag);
+        if constexpr (M > 4) if (slot == 4) rot_slot_any<T, M, 4>(amp, ga, gb, zeta, imag);
+        if constexpr (M > 5) if (slot == 5) rot_slot_any<T, M, 5>(amp, ga, gb, zeta, imag);
+        if (slot == kSlotDiag) rot_diag<T, M>(amp, ga, zeta);
     }
 }
 

@@ -33,6 +33,16 @@ prx_status hip_fail(hipError_t e, const char *what);
 // into one scale applied when the pass stores the state.  For x = 0 the
 // partner is k itself.
 //
+// Pair updates run in place: with a = psi[k] (the pair's element whose
+// basis bit is clear) and b = psi[k'],
+//     a <- a + tau_a s_b b,   then   b <- b + tau_b s_a a   (new a),
+// s_a, s_b the signs sigma; for imaginary tau both terms carry a factor i.
+// This equals the 2x2 update when b is stored divided by kappa = 1 -/+
+// tau^2 and a per-slot factor K is carried: tau_a = tau K, tau_b =
+// tau / (K kappa), K <- K kappa.  An element's stored value times the
+// product of K over the basis slots set in its coset label is its true
+// value; chunks (and span passes) record those K as `fscale`.
+//
 //   z      : z mask in the frame the kernel indexes (span: global index;
 //            tile: workgroup-local index)
 //   zhigh  : tile only: z restricted to the tile-index bits, for the sign
@@ -40,14 +50,16 @@ prx_status hip_fail(hipError_t e, const char *what);
 //   info   : bits 0-3  basis slot of x in the chunk (15 = diagonal, x = 0)
 //            bit  4    tau is imaginary (nY + 1 odd)
 //            bits 8-15 zeta: bit i = parity(basis_i & z)
-//   tau    : signed magnitude of tau (real or imaginary part)
+//   tau_a, tau_b : signed magnitudes (real or imaginary parts); for x = 0
+//            only tau_a is used (tan(phi))
 template <typename T>
 struct RotRec {
     uint64_t z;
     uint64_t zhigh;
     uint32_t info;
     uint32_t pad;
-    T tau;
+    T tau_a;
+    T tau_b;
 };
 
 static constexpr uint32_t kSlotDiag = 15;
@@ -64,7 +76,12 @@ struct ChunkRec {
     uint32_t basis[kMaxChunkRank];
     uint8_t pivot[kMaxChunkRank];
     uint8_t pad[2];
+    double fscale[kMaxChunkRank];  // pending per-slot factors K at the chunk's end
 };
+
+// Longest run of rotations in one chunk (bounds the pending factors: with
+// tau^2 <= 1/2 each kappa lies in [1/2, 3/2]).
+static constexpr int kMaxChunkRots = 64;
 
 // Kernel arguments of a span pass (one chunk in the global frame).
 struct SpanArgs {
@@ -72,7 +89,8 @@ struct SpanArgs {
     uint32_t pivot[kMaxChunkRank];
     uint32_t rot_begin, rot_count;
     int n;
-    double scale;  // product of the pass's cosines
+    double scale;                  // product of the pass's cosines
+    double fscale[kMaxChunkRank];  // pending per-slot factors K
 };
 
 // Kernel arguments of a tile pass.

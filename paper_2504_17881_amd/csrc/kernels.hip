@@ -127,11 +127,13 @@ __global__ void __launch_bounds__(256) k_span(Cx<T> *__restrict__ psi, SpanArgs 
     apply_rots<T, M>(amp, k0, 0, rots + a.rot_begin, a.rot_count);
     double sc = a.scale;
     if (renorm_in) sc *= *renorm_in;
-    const T s = (T)sc;
+    double F[1 << M];
+    pending_factors<M>(F, a.fscale);
     double nrm = 0.0;
     if (live) {
 #pragma unroll
         for (int v = 0; v < (1 << M); ++v) {
+            const T s = (T)(sc * F[v]);
             Cx<T> o;
             o.re = amp[v].re * s;
             o.im = amp[v].im * s;
@@ -185,8 +187,16 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
 #pragma unroll
         for (int v = 0; v < (1 << M); ++v) amp[v] = lds[k0 ^ X[v]];
         apply_rots<T, M>(amp, k0, tb, rots + ch.rot_begin, ch.rot_count);
+        double F[1 << M];
+        pending_factors<M>(F, ch.fscale);
 #pragma unroll
-        for (int v = 0; v < (1 << M); ++v) lds[k0 ^ X[v]] = amp[v];
+        for (int v = 0; v < (1 << M); ++v) {
+            const T f = (T)F[v];
+            Cx<T> o;
+            o.re = amp[v].re * f;
+            o.im = amp[v].im * f;
+            lds[k0 ^ X[v]] = o;
+        }
         __syncthreads();
     }
 

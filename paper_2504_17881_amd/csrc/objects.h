@@ -32,7 +32,7 @@ struct KRot {
 struct RotRecD {
     uint64_t z = 0, zhigh = 0;
     uint32_t info = 0;
-    double tau = 0.0;
+    double tau_a = 0.0, tau_b = 0.0;
 };
 
 enum PassKind { kPlain = 0, kSpan = 1, kTile = 2 };
@@ -44,6 +44,7 @@ struct Pass {
     int m = 0;
     uint64_t basis[kMaxChunkRank] = {};
     uint32_t pivot[kMaxChunkRank] = {};
+    double fscale[kMaxChunkRank] = {1, 1, 1, 1, 1, 1};
     // tile
     int B = 0, b = 0, g = 0;
     uint64_t vmask[kMaxVirtual] = {};

@@ -88,7 +88,7 @@ struct Gf2 {
     size_t rank() const { return orig.size(); }
 };
 
-// Tau and the info bits common to span and tile records.
+// Tau (signed magnitude of i^{nY+1} tan(phi)) and whether it is imaginary.
 struct Coef {
     double tau;
     uint32_t imag;
@@ -101,6 +101,32 @@ static Coef fused_coef(const KRot &r) {
     o.imag = (uint32_t)(mq & 1);
     return o;
 }
+
+// Pending per-slot factors of a chunk (see RotRec): builds the record of a
+// rotation in slot `slot` (kSlotDiag for x = 0) with zeta bits `zeta` and
+// updates the slot's factor.
+struct SlotScale {
+    double K[kMaxChunkRank] = {1, 1, 1, 1, 1, 1};
+    RotRecD record(const KRot &k, uint32_t slot, uint32_t zeta, uint64_t zframe,
+                   uint64_t zhigh) {
+        const Coef cf = fused_coef(k);
+        RotRecD rr;
+        rr.z = zframe;
+        rr.zhigh = zhigh;
+        rr.info = slot | (cf.imag << 4) | (zeta << 8);
+        if (slot == kSlotDiag) {
+            rr.tau_a = cf.tau;
+            rr.tau_b = 0.0;
+            return rr;
+        }
+        const double zs = ((zeta >> slot) & 1u) ? -1.0 : 1.0;
+        const double kappa = cf.imag ? 1.0 + zs * cf.tau * cf.tau : 1.0 - zs * cf.tau * cf.tau;
+        rr.tau_a = cf.tau * K[slot];
+        rr.tau_b = cf.tau / (K[slot] * kappa);
+        K[slot] *= kappa;
+        return rr;
+    }
+};
 
 static PlainArgs plain_args(int n, const KRot &r) {
     PlainArgs a;
@@ -133,7 +159,8 @@ struct Builder {
         Gf2 g;
         std::vector<uint64_t> basis;
         size_t j = p;
-        for (; j < end && (int)(j - p) < cfg.max_fuse; ++j) {
+        const int cap = std::min(cfg.max_fuse, kMaxChunkRots);
+        for (; j < end && (int)(j - p) < cap; ++j) {
             const uint64_t x = R[j].x;
             if (x == 0 || std::find(basis.begin(), basis.end(), x) != basis.end()) continue;
             if ((int)basis.size() < mmax && !g.contains(x)) {
@@ -203,7 +230,8 @@ struct Builder {
             if (r.x == 0 || std::find(basis.begin(), basis.end(), r.x) != basis.end()) return true;
             return (int)basis.size() < cfg.span_m && !g.contains(r.x);
         };
-        for (; j < stop && (int)(j - p) < cfg.max_fuse; ++j) {
+        const int cap = std::min(cfg.max_fuse, kMaxChunkRots);
+        for (; j < stop && (int)(j - p) < cap; ++j) {
             if (!fits(R[j]) && !pull_forward(j, fits)) break;
             const uint64_t x = R[j].x;
             if (x && std::find(basis.begin(), basis.end(), x) == basis.end()) {
@@ -233,21 +261,17 @@ struct Builder {
             ps.pivot[i] = piv[i];
         }
         double scale = 1.0;
+        SlotScale ss;
         for (size_t r = p; r < j; ++r) {
             const KRot &k = R[r];
-            const Coef cf = fused_coef(k);
             scale *= std::cos(k.phi);
             uint32_t slot = kSlotDiag;
             if (k.x) slot = (uint32_t)(std::find(basis.begin(), basis.end(), k.x) - basis.begin());
             uint32_t zeta = 0;
             for (int i = 0; i < ps.m; ++i) zeta |= par(basis[i] & k.z) << i;
-            RotRecD rr;
-            rr.z = k.z;
-            rr.zhigh = 0;
-            rr.info = slot | (cf.imag << 4) | (zeta << 8);
-            rr.tau = cf.tau;
-            recs.push_back(rr);
+            recs.push_back(ss.record(k, slot, zeta, k.z, 0));
         }
+        for (int i = 0; i < kMaxChunkRank; ++i) ps.fscale[i] = ss.K[i];
         ps.scale = scale;
         P.passes.push_back(ps);
         P.span_passes++;
@@ -318,7 +342,7 @@ struct Builder {
             Gf2 cg;
             std::vector<uint32_t> basis;
             size_t q = r;
-            for (; q < j; ++q) {
+            for (; q < j && (int)(q - r) < kMaxChunkRots; ++q) {
                 const uint32_t x = loc[q - p].x;
                 if (x == 0 || std::find(basis.begin(), basis.end(), x) != basis.end()) continue;
                 if ((int)basis.size() < cfg.m && !cg.contains(x)) {
@@ -344,22 +368,18 @@ struct Builder {
                 ch.pivot[i] = (uint8_t)piv[i];
             }
             P.chunks.push_back(ch);
+            SlotScale ss;
             for (size_t t = r; t < q; ++t) {
                 const KRot &k = R[t];
                 const Loc &L = loc[t - p];
-                const Coef cf = fused_coef(k);
                 scale *= std::cos(k.phi);
                 uint32_t slot = kSlotDiag;
                 if (L.x) slot = (uint32_t)(std::find(basis.begin(), basis.end(), L.x) - basis.begin());
                 uint32_t zeta = 0;
                 for (int i = 0; i < cfg.m; ++i) zeta |= par((uint64_t)basis[i] & L.z) << i;
-                RotRecD rr;
-                rr.z = L.z;
-                rr.zhigh = L.zhigh;
-                rr.info = slot | (cf.imag << 4) | (zeta << 8);
-                rr.tau = cf.tau;
-                recs.push_back(rr);
+                recs.push_back(ss.record(k, slot, zeta, L.z, L.zhigh));
             }
+            for (int i = 0; i < kMaxChunkRank; ++i) P.chunks.back().fscale[i] = ss.K[i];
             r = q;
         }
         ps.c1 = P.chunks.size();
@@ -518,7 +538,8 @@ static void pack_records(prx_plan &P, const std::vector<RotRecD> &recs) {
         r.z = recs[i].z;
         r.zhigh = recs[i].zhigh;
         r.info = recs[i].info;
-        r.tau = (T)recs[i].tau;
+        r.tau_a = (T)recs[i].tau_a;
+        r.tau_b = (T)recs[i].tau_b;
         out[i] = r;
     }
 }
@@ -559,14 +580,19 @@ static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtyp
                 return fail(PRX_ERR_INVALID, "bad planner option");
             }
         }
+        // Fused plans apply a rotation in k equal pieces, exp(i phi P) =
+        // exp(i (phi/k) P)^k, with k the least integer giving |tan(phi/k)| <=
+        // 1/sqrt(2): the pair update's kappa then stays in [1/2, 3/2] and
+        // every cosine is at least 0.8 in magnitude.
         P->rots.reserve(end - begin);
+        const double tmax = 0.70710678118654752, amax = 0.61547970867038734;  // atan(tmax)
         for (size_t j = begin; j < end; ++j) {
-            KRot k{sched->x[j], sched->z[j], sched->phi[j], j};
-            if (fused && std::fabs(std::cos(k.phi)) < 0.5) {
-                k.phi = sched->phi[j] * 0.5;
-                P->rots.push_back(k);
-            }
-            P->rots.push_back(k);
+            const double phi = sched->phi[j];
+            int pieces = 1;
+            if (fused && !(std::fabs(std::tan(phi)) <= tmax))
+                pieces = (int)std::ceil(std::fabs(phi) / amax);
+            const double part = phi / pieces;
+            for (int q = 0; q < pieces; ++q) P->rots.push_back(KRot{sched->x[j], sched->z[j], part, j});
         }
         P->end = P->rots.size();
         Builder bld(*P, P->end);
@@ -713,6 +739,7 @@ static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws
             a.rot_count = (uint32_t)(ps.r1 - ps.r0);
             a.n = P->n;
             a.scale = ps.scale;
+            for (int k = 0; k < kMaxChunkRank; ++k) a.fscale[k] = ps.fscale[k];
             e = launch_span(P->dtype, ps.m, psi, a, rots, rin, nout, s, &blocks);
         } else {
             TileArgs a;
@@ -800,6 +827,7 @@ prx_status prx_plan_pass(const prx_plan *P, size_t i, prx_pass_info *o) {
     for (int k = 0; k < (1 << kMaxVirtual); ++k) o->vcomb[k] = ps.vcomb[k];
     for (int k = 0; k < kMaxVirtual; ++k) o->tpivot[k] = ps.tpivot[k];
     o->scale = ps.scale;
+    for (int k = 0; k < kMaxChunkRank; ++k) o->fscale[k] = ps.fscale[k];
     o->norm_out = ps.norm_out;
     o->renorm_in = ps.renorm_in;
     return PRX_OK;
@@ -814,6 +842,7 @@ prx_status prx_plan_chunk(const prx_plan *P, size_t i, prx_chunk_info *o) {
         o->basis[k] = c.basis[k];
         o->pivot[k] = c.pivot[k];
     }
+    for (int k = 0; k < kMaxChunkRank; ++k) o->fscale[k] = c.fscale[k];
     o->rot_begin = c.rot_begin;
     o->rot_count = c.rot_count;
     return PRX_OK;
@@ -835,7 +864,8 @@ prx_status prx_plan_rotation(const prx_plan *P, size_t i, prx_rot_info *o) {
         o->slot = r.info & 15u;
         o->imag = (r.info >> 4) & 1u;
         o->zeta = (r.info >> 8) & 0xffu;
-        o->tau = r.tau;
+        o->tau = r.tau_a;
+        o->tau_b = r.tau_b;
     } else {
         const RotRec<double> &r = reinterpret_cast<const RotRec<double> *>(P->rot_table.data())[i];
         o->zframe = r.z;
@@ -843,7 +873,8 @@ prx_status prx_plan_rotation(const prx_plan *P, size_t i, prx_rot_info *o) {
         o->slot = r.info & 15u;
         o->imag = (r.info >> 4) & 1u;
         o->zeta = (r.info >> 8) & 0xffu;
-        o->tau = r.tau;
+        o->tau = r.tau_a;
+        o->tau_b = r.tau_b;
     }
     return PRX_OK;
 }

@@ -75,20 +75,20 @@ class prx_pass_info(ctypes.Structure):
                 ("m", ctypes.c_int),
                 ("basis", ctypes.c_uint64 * 6), ("pivot", ctypes.c_uint32 * 6),
                 ("vcomb", ctypes.c_uint64 * 8), ("tpivot", ctypes.c_uint32 * 3),
-                ("scale", ctypes.c_double), ("norm_out", ctypes.c_int),
-                ("renorm_in", ctypes.c_int)]
+                ("scale", ctypes.c_double), ("fscale", ctypes.c_double * 6),
+                ("norm_out", ctypes.c_int), ("renorm_in", ctypes.c_int)]
 
 
 class prx_chunk_info(ctypes.Structure):
     _fields_ = [("basis", ctypes.c_uint32 * 6), ("pivot", ctypes.c_uint32 * 6),
-                ("rot_begin", _sz), ("rot_count", _sz)]
+                ("fscale", ctypes.c_double * 6), ("rot_begin", _sz), ("rot_count", _sz)]
 
 
 class prx_rot_info(ctypes.Structure):
     _fields_ = [("x", ctypes.c_uint64), ("z", ctypes.c_uint64), ("phi", ctypes.c_double),
                 ("source", _sz), ("zframe", ctypes.c_uint64), ("zhigh", ctypes.c_uint64),
                 ("slot", ctypes.c_uint32), ("imag", ctypes.c_uint32),
-                ("zeta", ctypes.c_uint32), ("tau", ctypes.c_double)]
+                ("zeta", ctypes.c_uint32), ("tau", ctypes.c_double), ("tau_b", ctypes.c_double)]
 
 
 def _sig(name, res, *args):
@@ -340,7 +340,7 @@ def prx_plan_pass(plan: int, i: int) -> dict:
     o = prx_pass_info()
     _check(_lib.prx_plan_pass(plan, i, ctypes.byref(o)))
     d = {f: getattr(o, f) for f, _ in prx_pass_info._fields_}
-    for k in ("basis", "pivot", "vcomb", "tpivot"):
+    for k in ("basis", "pivot", "vcomb", "tpivot", "fscale"):
         d[k] = list(d[k])
     return d
 
@@ -351,6 +351,7 @@ def prx_plan_chunk(plan: int, i: int) -> dict:
     d = {f: getattr(o, f) for f, _ in prx_chunk_info._fields_}
     d["basis"] = list(d["basis"])
     d["pivot"] = list(d["pivot"])
+    d["fscale"] = list(d["fscale"])
     return d
 
 

@@ -38,17 +38,22 @@ def _xcomb(basis, m):
 
 
 def _apply_records(amp, recs, s0_of, m):
-    """amp: list of 2^m complex arrays (same shape); recs: rotation records."""
+    """amp: list of 2^m complex arrays (same shape); recs: rotation records.
+
+    Pair (a, b) of slot I (a without, b with bit I): a <- a + u ga s_b b, then
+    b <- b + u gb s_a a with the new a (u = 1 or i, s the signs, ga and gb the
+    records' tau_a and tau_b with the per-element sign s0)."""
     for r in recs:
         s0 = s0_of(r)
-        g = r["tau"] * (1.0 - 2.0 * s0)
+        ga = r["tau"] * (1.0 - 2.0 * s0)
+        gb = r["tau_b"] * (1.0 - 2.0 * s0)
         unit = 1j if r["imag"] else 1.0
         zeta = r["zeta"]
         slot = r["slot"]
         if slot == 15:
             for v in range(1 << m):
                 sv = 1.0 - 2.0 * (bin(v & zeta).count("1") & 1)
-                amp[v] = amp[v] + unit * g * sv * amp[v]
+                amp[v] = amp[v] + unit * ga * sv * amp[v]
             continue
         I = 1 << slot
         for v in range(1 << m):
@@ -57,10 +62,14 @@ def _apply_records(amp, recs, s0_of, m):
             w = v | I
             sv = 1.0 - 2.0 * (bin(v & zeta).count("1") & 1)
             sw = 1.0 - 2.0 * (bin(w & zeta).count("1") & 1)
-            av, aw = amp[v], amp[w]
-            amp[v] = av + unit * g * sw * aw
-            amp[w] = aw + unit * g * sv * av
+            amp[v] = amp[v] + unit * ga * sw * amp[w]
+            amp[w] = amp[w] + unit * gb * sv * amp[v]
     return amp
+
+
+def _pending(fscale, m):
+    """Factor of coset label v: the product of fscale over the bits set in v."""
+    return [math.prod(fscale[i] for i in range(m) if v >> i & 1) for v in range(1 << m)]
 
 
 def _plain(psi, n, r):
@@ -97,8 +106,9 @@ def run_plan(plan: int, psi0: np.ndarray, n: int) -> np.ndarray:
             idx = [k0 ^ np.uint64(X[v]) for v in range(1 << m)]
             amp = [psi[i] for i in idx]
             amp = _apply_records(amp, recs, lambda r: _parity(k0 & np.uint64(r["zframe"])), m)
+            F = _pending(ps["fscale"], m)
             for v in range(1 << m):
-                psi[idx[v]] = amp[v] * scale
+                psi[idx[v]] = amp[v] * (scale * F[v])
         else:
             B, b, g, m = ps["B"], ps["b"], ps["g"], ps["m"]
             nwg = 1 << (n - B)
@@ -120,8 +130,9 @@ def run_plan(plan: int, psi0: np.ndarray, n: int) -> np.ndarray:
                     return (_parity(k0 & np.uint64(r["zframe"]))[None, :] ^
                             _parity(tb & np.uint64(r["zhigh"]))[:, None])
                 amp = _apply_records(amp, crecs, s0_of, m)
+                F = _pending(ch["fscale"], m)
                 for v in range(1 << m):
-                    lds[:, idx[v].astype(np.int64)] = amp[v]
+                    lds[:, idx[v].astype(np.int64)] = amp[v] * F[v]
             psi[gidx] = lds * scale
         if ps["norm_out"]:
             pending = 1.0 / math.sqrt(float(np.sum(np.abs(psi) ** 2)))

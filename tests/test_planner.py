@@ -26,13 +26,12 @@ def _check_composition(plan, x, z, phi, commuting=False):
     assert sorted(by_src) == list(range(len(x)))
     for j, rs in by_src.items():
         assert all(r["x"] == x[j] and r["z"] == z[j] for r in rs)
-        assert len(rs) in (1, 2)
         tot = sum(r["phi"] for r in rs)
-        assert abs(tot - phi[j]) <= 4e-16 * max(1.0, abs(phi[j]))
-        if len(rs) == 2:
-            assert abs(math.cos(phi[j])) < 0.5 and rs[0]["phi"] == rs[1]["phi"]
-        assert all(abs(math.cos(r["phi"])) >= 0.5 or info["passes"] == info["plain_passes"]
-                   for r in rs)
+        assert abs(tot - phi[j]) <= 1e-15 * max(1.0, abs(phi[j])) * len(rs)
+        if len(rs) > 1:  # equal pieces, only for large angles
+            assert abs(math.tan(phi[j])) > 2 ** -0.5 and len({r["phi"] for r in rs}) == 1
+        fused = info["passes"] != info["plain_passes"]
+        assert all(abs(math.tan(r["phi"])) <= 2 ** -0.5 + 1e-15 or not fused for r in rs)
     order = [r["source"] for r in rots]
     if not commuting:
         assert order == sorted(order)
