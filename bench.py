@@ -118,6 +118,9 @@ def main() -> int:
                     help="run the autotuner on the first --tune-rotations rotations first and "
                          "save its cache to this path")
     ap.add_argument("--tune-rotations", type=int, default=1000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="GIB",
+                    help="first run torch copies of GIB GiB (3 launches): the known-size "
+                         "reference that scales hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path is a "
@@ -140,6 +143,18 @@ def main() -> int:
     k0 = synth.basis_index(n)
     dev = torch.device("cuda:0")
     print(f"[bench] n={n} L={L} rotations={len(sx)}", file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 copies of {nbytes} B (read {nbytes} B, "
+              f"write {nbytes} B each)", file=sys.stderr, flush=True)
+        del src, dst
+        torch.cuda.empty_cache()
 
     # ---------------- planner settings: tuned cache (or a fresh tuning run)
     tuned = None

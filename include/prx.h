@@ -147,9 +147,10 @@ void prx_sched_destroy(prx_sched *s);
 typedef struct {
     int tile_qubits;     /* qubits held by one workgroup in the tile kernel (default per dtype) */
     int chunk_rank;      /* rotations' X-span rank a thread holds in registers (default 4) */
-    int max_fuse;        /* max rotations per tile pass (default 64) */
+    int max_fuse;        /* max rotations per tile pass (default 128) */
     int span_max;        /* max rotations per span pass (default: chunk_rank and repeats) */
-    int max_virtual;     /* max high-qubit XOR masks gathered into a tile (default 2) */
+    int max_virtual;     /* max high-qubit XOR masks gathered into a tile, <= 8; the tile
+                            keeps at least 16 contiguous amplitudes (default 8) */
     int renorm_every;    /* C64: renormalise in FP64 every k passes (default 1; -1 = never) */
     int commuting;       /* 1: planner may swap adjacent commuting rotations (default 0) */
 } prx_plan_opts;
@@ -200,8 +201,9 @@ prx_status prx_plan_execute_timed(const prx_plan *plan, void *psi, void *ws, siz
  * Passes: kind 0 = single-rotation sweep, 1 = span pass (one chunk in the
  * global index frame, `basis`/`pivot` valid), 2 = tile pass (workgroup
  * frame of B bits = b low qubits + g virtual qubits; workgroup w holds the
- * tiles (t XOR vcomb[v]) for v < 2^g, t = w with zeros inserted at the
- * ascending `tpivot` bits of the tile index; chunks [chunk_begin, +count)).
+ * tiles t XOR (XOR of vmask[i] over the bits i set in v) for v < 2^g, t = w
+ * with zeros inserted at the ascending `tpivot` bits of the tile index;
+ * chunks [chunk_begin, +count)).
  * `scale` is the product of the pass's cosines, applied at its store. */
 typedef struct {
     int kind;
@@ -210,8 +212,8 @@ typedef struct {
     int B, b, g, m;                   /* tile qubits, low qubits, virtual qubits, rank */
     uint64_t basis[6];                /* span: X-mask basis (global frame) */
     uint32_t pivot[6];                /* span: ascending pivot bits of its echelon form */
-    uint64_t vcomb[8];                /* tile: XOR of virtual masks per combination */
-    uint32_t tpivot[3];               /* tile: ascending pivot bits in tile-index space */
+    uint64_t vmask[8];                /* tile: virtual masks (tile-index space), g used */
+    uint32_t tpivot[8];               /* tile: ascending pivot bits of their echelon form */
     double scale;
     double fscale[6];                 /* span: pending per-slot factors (see prx_rot_info) */
     int norm_out, renorm_in;          /* C64 renormalisation hand-off */

@@ -64,7 +64,10 @@ struct RotRec {
 
 static constexpr uint32_t kSlotDiag = 15;
 static constexpr int kMaxChunkRank = 6;
-static constexpr int kMaxVirtual = 3;
+// Virtual qubits of a tile pass: at most 8 XOR masks of tile-index bits, and
+// at least 16 contiguous amplitudes per tile (128 B at complex64).
+static constexpr int kMaxVirtual = 8;
+static constexpr int kMinTileLow = 4;
 
 // A chunk of a tile pass: up to kMaxChunkRank basis directions in the
 // workgroup-local frame, with their pivot bits (reduced echelon form,
@@ -95,8 +98,9 @@ struct SpanArgs {
 
 // Kernel arguments of a tile pass.
 struct TileArgs {
-    uint64_t vcomb[1 << kMaxVirtual];  // XOR of the virtual masks selected by each combination
-    uint32_t tpivot[kMaxVirtual];      // pivot bits (tile-index space) of the echelon virtual masks
+    uint64_t vmask[kMaxVirtual];  // virtual masks (tile-index space): tile v of a workgroup's
+                                  // set is t XOR (the masks selected by the bits of v)
+    uint8_t tpivot[kMaxVirtual];  // pivot bits of the masks' echelon form, ascending
     int n, b, g;
     uint32_t chunk_begin, chunk_count;
     double scale;

@@ -155,22 +155,37 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
                                                       const ChunkRec *__restrict__ chunks,
                                                       const double *__restrict__ renorm_in,
                                                       double *__restrict__ norm_out) {
-    constexpr int NT = 1 << (B - M);
+    constexpr int NT = 1 << (B - M);  // threads
+    constexpr int PER = 1 << M;       // amplitudes per thread (tile-set 2^B)
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Cx<T> *lds = reinterpret_cast<Cx<T> *>(lds_raw);
     __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+    __shared__ uint64_t vtab[1 << kMaxVirtual];  // tile-index offset of each tile of the set
     const uint32_t tid = threadIdx.x;
 
     uint64_t tb = blockIdx.x;
     for (int i = 0; i < a.g; ++i) tb = insert_zero64(tb, a.tpivot[i]);
     const int b = a.b;
-    const uint32_t tile_len = 1u << b;
-    const int ncomb = 1 << a.g;
+    const uint32_t low = (1u << b) - 1u;
+    for (uint32_t v = tid; v < (1u << a.g); v += NT) {
+        uint64_t c = 0;
+        for (int i = 0; i < a.g; ++i)
+            if (v >> i & 1) c ^= a.vmask[i];
+        vtab[v] = c;
+    }
+    __syncthreads();
 
-    for (int vb = 0; vb < ncomb; ++vb) {
-        const Cx<T> *src = psi + ((tb ^ a.vcomb[vb]) << b);
-        Cx<T> *dst = lds + ((uint32_t)vb << b);
-        for (uint32_t off = tid; off < tile_len; off += NT) dst[off] = src[off];
+    // LDS slot s = (v << b) | offset holds amplitude ((t ^ vtab[v]) << b) | offset.
+    // Every thread issues all its loads before the first LDS store.
+    {
+        Cx<T> r[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t s = tid + (uint32_t)u * NT;
+            r[u] = psi[((tb ^ vtab[s >> b]) << b) | (s & low)];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
     }
     __syncthreads();
 
@@ -204,14 +219,17 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
     if (renorm_in) sc *= *renorm_in;
     const T s = (T)sc;
     double nrm = 0.0;
-    for (int vb = 0; vb < ncomb; ++vb) {
-        Cx<T> *dst = psi + ((tb ^ a.vcomb[vb]) << b);
-        const Cx<T> *src = lds + ((uint32_t)vb << b);
-        for (uint32_t off = tid; off < tile_len; off += NT) {
-            Cx<T> o = src[off];
+    {
+        Cx<T> r[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) r[u] = lds[tid + (uint32_t)u * NT];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t sl = tid + (uint32_t)u * NT;
+            Cx<T> o = r[u];
             o.re *= s;
             o.im *= s;
-            dst[off] = o;
+            psi[((tb ^ vtab[sl >> b]) << b) | (sl & low)] = o;
             nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
         }
     }

@@ -48,7 +48,6 @@ struct Pass {
     // tile
     int B = 0, b = 0, g = 0;
     uint64_t vmask[kMaxVirtual] = {};
-    uint64_t vcomb[1 << kMaxVirtual] = {};
     uint32_t tpivot[kMaxVirtual] = {};
     size_t c0 = 0, c1 = 0;  // chunks
     double scale = 1.0;

@@ -305,12 +305,6 @@ struct Builder {
         ps.g = g;
         ps.m = cfg.m;
         for (int i = 0; i < g; ++i) ps.vmask[i] = M.orig[i];
-        for (int vb = 0; vb < (1 << g); ++vb) {
-            uint64_t v = 0;
-            for (int i = 0; i < g; ++i)
-                if (vb >> i & 1) v ^= M.orig[i];
-            ps.vcomb[vb] = v;
-        }
         auto tp = M.pivots();
         for (int i = 0; i < g; ++i) ps.tpivot[i] = tp[i];
         ps.c0 = P.chunks.size();
@@ -406,7 +400,7 @@ struct Builder {
     Reach reach_from(size_t p, bool tile_ok) const {
         Reach r{p + span_len(p, cfg.span_m), kSpan, 0};
         if (tile_ok) {
-            for (int g = 0; g <= cfg.max_virtual && g <= P.n - cfg.B; ++g) {
+            for (int g = 0; g <= cfg.max_virtual && g <= P.n - cfg.B && cfg.B - g >= kMinTileLow; ++g) {
                 const size_t e = p + tile_len(p, g);
                 if (e > r.end) r = Reach{e, kTile, g};
             }
@@ -475,7 +469,7 @@ struct Builder {
             size_t ft = 0;
             int gbest = 0;
             if (tile_ok) {
-                for (int g = 0; g <= cfg.max_virtual && g <= P.n - cfg.B; ++g) {
+                for (int g = 0; g <= cfg.max_virtual && g <= P.n - cfg.B && cfg.B - g >= kMinTileLow; ++g) {
                     const size_t f = tile_len(p, g);
                     if (f > ft) {
                         ft = f;
@@ -511,8 +505,8 @@ static void default_cfg(prx_dtype dt, PlanCfg &c) {
     c.B = (dt == PRX_C64) ? 12 : 11;
     c.m = 4;
     c.span_m = 4;
-    c.max_fuse = 64;
-    c.max_virtual = 2;
+    c.max_fuse = 128;
+    c.max_virtual = kMaxVirtual;
     c.renorm_every = (dt == PRX_C64) ? 1 : -1;
     c.commuting = false;
 }
@@ -744,8 +738,10 @@ static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws
         } else {
             TileArgs a;
             std::memset(&a, 0, sizeof(a));
-            for (int k = 0; k < (1 << ps.g); ++k) a.vcomb[k] = ps.vcomb[k];
-            for (int k = 0; k < ps.g; ++k) a.tpivot[k] = ps.tpivot[k];
+            for (int k = 0; k < ps.g; ++k) {
+                a.vmask[k] = ps.vmask[k];
+                a.tpivot[k] = (uint8_t)ps.tpivot[k];
+            }
             a.n = P->n;
             a.b = ps.b;
             a.g = ps.g;
@@ -824,8 +820,10 @@ prx_status prx_plan_pass(const prx_plan *P, size_t i, prx_pass_info *o) {
         o->basis[k] = ps.basis[k];
         o->pivot[k] = ps.pivot[k];
     }
-    for (int k = 0; k < (1 << kMaxVirtual); ++k) o->vcomb[k] = ps.vcomb[k];
-    for (int k = 0; k < kMaxVirtual; ++k) o->tpivot[k] = ps.tpivot[k];
+    for (int k = 0; k < kMaxVirtual; ++k) {
+        o->vmask[k] = ps.vmask[k];
+        o->tpivot[k] = ps.tpivot[k];
+    }
     o->scale = ps.scale;
     for (int k = 0; k < kMaxChunkRank; ++k) o->fscale[k] = ps.fscale[k];
     o->norm_out = ps.norm_out;

@@ -86,7 +86,8 @@ prx_status prx_autotune(void *psi, int n, prx_dtype dtype, const prx_sched *sche
     std::vector<prx_plan_opts> cands;
     for (const Shape &sh : shapes) {
         if (!tile_supported(dtype, sh.B, sh.m) || n < sh.B + 1) continue;
-        for (int g : {1, 2, 3})
+        for (int g : {1, 2, 3, 5, 8}) {
+            if (sh.B - g < kMinTileLow) continue;
             for (int f : {64, 128}) {
                 prx_plan_opts o;
                 std::memset(&o, 0, sizeof(o));
@@ -97,6 +98,7 @@ prx_status prx_autotune(void *psi, int n, prx_dtype dtype, const prx_sched *sche
                 o.span_max = 4;
                 cands.push_back(o);
             }
+        }
     }
     if (cands.empty()) {  // too small for tiles: span rank only
         for (int r : {2, 3, 4, 5}) {

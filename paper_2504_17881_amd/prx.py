@@ -74,7 +74,7 @@ class prx_pass_info(ctypes.Structure):
                 ("B", ctypes.c_int), ("b", ctypes.c_int), ("g", ctypes.c_int),
                 ("m", ctypes.c_int),
                 ("basis", ctypes.c_uint64 * 6), ("pivot", ctypes.c_uint32 * 6),
-                ("vcomb", ctypes.c_uint64 * 8), ("tpivot", ctypes.c_uint32 * 3),
+                ("vmask", ctypes.c_uint64 * 8), ("tpivot", ctypes.c_uint32 * 8),
                 ("scale", ctypes.c_double), ("fscale", ctypes.c_double * 6),
                 ("norm_out", ctypes.c_int), ("renorm_in", ctypes.c_int)]
 
@@ -340,7 +340,7 @@ def prx_plan_pass(plan: int, i: int) -> dict:
     o = prx_pass_info()
     _check(_lib.prx_plan_pass(plan, i, ctypes.byref(o)))
     d = {f: getattr(o, f) for f, _ in prx_pass_info._fields_}
-    for k in ("basis", "pivot", "vcomb", "tpivot", "fscale"):
+    for k in ("basis", "pivot", "vmask", "tpivot", "fscale"):
         d[k] = list(d[k])
     return d
 

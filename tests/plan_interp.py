@@ -114,8 +114,12 @@ def run_plan(plan: int, psi0: np.ndarray, n: int) -> np.ndarray:
             nwg = 1 << (n - B)
             tb = _insert_zeros(np.arange(nwg, dtype=np.uint64), ps["tpivot"][:g])
             off = np.arange(1 << b, dtype=np.uint64)
+            vcomb = [0] * (1 << g)  # XOR of the virtual masks selected by each tile of the set
+            for vb in range(1, 1 << g):
+                low = (vb & -vb).bit_length() - 1
+                vcomb[vb] = vcomb[vb & (vb - 1)] ^ int(ps["vmask"][low])
             gidx = np.concatenate(
-                [((tb ^ np.uint64(ps["vcomb"][vb]))[:, None] << np.uint64(b)) | off[None, :]
+                [((tb ^ np.uint64(vcomb[vb]))[:, None] << np.uint64(b)) | off[None, :]
                  for vb in range(1 << g)], axis=1)  # (nwg, 2^B) global index of lds slot
             lds = psi[gidx]
             for c in range(ps["chunk_begin"], ps["chunk_begin"] + ps["chunk_count"]):

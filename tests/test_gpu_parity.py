@@ -68,6 +68,8 @@ SHAPES = [
     dict(tile_qubits=11, chunk_rank=4, max_virtual=1),
     dict(tile_qubits=12, chunk_rank=4, max_virtual=2),
     dict(tile_qubits=12, chunk_rank=5),
+    dict(tile_qubits=10, chunk_rank=4, max_virtual=5, span_max=2),
+    dict(tile_qubits=11, chunk_rank=4, max_virtual=4, span_max=2),
     dict(span_max=1),
     dict(span_max=2),
     dict(span_max=3),
@@ -92,6 +94,34 @@ def test_fused_shapes_jw_trotter(opts, dtype):
     psi0 = synth.gaussian_state(n, 12)
     ref = sv.c_apply_rotations(psi0, rx, rz, rp)
     print(f"[shapes {opts} dtype={dtype}]", flush=True)
+    t = to_dev(psi0, dtype)
+    info = apply(t, n, dtype, s, P.PRX_FUSED, opts=opts)
+    err = rel_err(to_host(t), ref)
+    tol = 1e-12 if dtype == P.PRX_C128 else c64_tol(len(rx))
+    assert err <= tol, (err, info)
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
+
+
+@pytest.mark.parametrize("dtype", [P.PRX_C128, P.PRX_C64])
+@pytest.mark.parametrize("g", [6, 8])
+def test_many_virtual_qubits(g, dtype):
+    """Tile-sets of 2^g tiles with as few as 16 contiguous amplitudes: n = 20,
+    12-qubit tile frame, spans limited so that tiles take the high X parts."""
+    n = 20
+    x, z, h = synth.jw_hamiltonian(n, 300, 21)
+    H = P.prx_ham_create(n, x, z, h)
+    s = P.prx_sched_trotter(H, 1, 2.0, 1, P.PRX_REORDER_SUFFIX)
+    _, rx, rz, rp = P.prx_sched_view(s)
+    psi0 = synth.gaussian_state(n, 22)
+    ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+    opts = dict(tile_qubits=12 if dtype == P.PRX_C64 else 11, chunk_rank=4, max_virtual=g,
+                span_max=2, max_fuse=128)
+    print(f"[many virtual g={g} dtype={dtype}]", flush=True)
+    pl = P.prx_plan_create(s, n, dtype, 0, len(rx), P.PRX_FUSED, opts)
+    gs = [P.prx_plan_pass(pl, i)["g"] for i in range(P.prx_plan_get_info(pl)["passes"])]
+    assert max(gs) >= min(g, 5)
+    P.prx_plan_destroy(pl)
     t = to_dev(psi0, dtype)
     info = apply(t, n, dtype, s, P.PRX_FUSED, opts=opts)
     err = rel_err(to_host(t), ref)

@@ -57,7 +57,10 @@ def _check_closure(plan, n):
                 assert r["x"] == 0 or r["x"] == basis[r["slot"]]
         elif ps["kind"] == 2:
             b, g = ps["b"], ps["g"]
-            span = {ps["vcomb"][v] for v in range(1 << g)}
+            span = {0}
+            for i in range(g):
+                span |= {s ^ int(ps["vmask"][i]) for s in span}
+            assert len(span) == 1 << g  # independent masks
             for r in rots:
                 assert (r["x"] >> b) in span
 
@@ -83,11 +86,13 @@ def test_interpreter_matches_oracle_random(n, M, dtype, opts):
     P.prx_sched_destroy(s)
 
 
-@pytest.mark.parametrize("opts", [None, dict(max_virtual=1), dict(tile_qubits=10, chunk_rank=4),
-                                  dict(tile_qubits=12, chunk_rank=5), dict(commuting=1),
-                                  dict(max_fuse=7)])
-def test_interpreter_matches_oracle_jw_trotter(opts):
-    n = 14
+@pytest.mark.parametrize("n,opts", [
+    (14, None), (14, dict(max_virtual=1)), (14, dict(tile_qubits=10, chunk_rank=4)),
+    (14, dict(tile_qubits=12, chunk_rank=5)), (14, dict(commuting=1)), (14, dict(max_fuse=7)),
+    (16, dict(tile_qubits=10, chunk_rank=4, max_virtual=6)),
+    (18, dict(tile_qubits=12, chunk_rank=4, max_virtual=6, span_max=2)),
+])
+def test_interpreter_matches_oracle_jw_trotter(n, opts):
     x, z, h = synth.jw_hamiltonian(n, 300, 7)
     H = P.prx_ham_create(n, x, z, h)
     s = P.prx_sched_trotter(H, 1, 2.0, 2, P.PRX_REORDER_SUFFIX)
