@@ -219,11 +219,13 @@ typedef struct {
     int norm_out, renorm_in;          /* C64 renormalisation hand-off */
 } prx_pass_info;
 
-/* A chunk of a tile pass: basis directions in the workgroup frame and the
- * ascending pivot bits used to enumerate coset representatives. */
+/* A chunk of a tile pass: basis directions in the workgroup frame; thread t
+ * of the workgroup holds the coset k0(t) XOR span(basis) with k0(t) the XOR
+ * of cvec[i] over the bits i set in t (cvec[0 .. B-m-1] span a complement
+ * of the basis span). */
 typedef struct {
     uint32_t basis[6];
-    uint32_t pivot[6];
+    uint32_t cvec[8];
     double fscale[6];                 /* pending per-slot factors at the chunk's end */
     size_t rot_begin, rot_count;
 } prx_chunk_info;
@@ -238,14 +240,22 @@ typedef struct {
  * held divided by kappa = 1 -/+ tau^2, tracked as per-slot factors K
  * (tau_a = tau K, tau_b = tau / (K kappa), K <- K kappa); the true value of
  * the element with coset label v is its stored value times the product of
- * fscale[i] over the bits i set in v. */
+ * fscale[i] over the bits i set in v.
+ *
+ * Chunks of rank m <= 4 (static_sign = 1) run one compiled update per
+ * variant var = slot 2^m + imag 2^(m-1) + zp (m 2^m for x = 0), zp being
+ * zeta with bit `slot` removed; tau is then stored multiplied by
+ * (-1)^zeta_slot, and pair (v, v | 2^slot) takes both coefficients times
+ * s0 (-1)^parity(c(v) & zp), s0 the sign of the coset representative and
+ * c(v) = v with bit `slot` removed. */
 typedef struct {
     uint64_t x, z;
     double phi;
     size_t source;
     uint64_t zframe, zhigh;
     uint32_t slot, imag, zeta;
-    double tau;      /* tau_a (for x = 0: tan(phi)) */
+    uint32_t var, static_sign;
+    double tau;      /* tau_a as stored (for x = 0: tan(phi)) */
     double tau_b;
 } prx_rot_info;
 

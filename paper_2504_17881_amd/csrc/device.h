@@ -35,6 +35,10 @@ __device__ __forceinline__ double pin(double v) {
     asm volatile("" : "+v"(v));
     return v;
 }
+__device__ __forceinline__ uint32_t pin(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
 
 // Flip the sign of v when bit 0 of p is set (an XOR on the sign bit).
 __device__ __forceinline__ float flip(float v, uint32_t p) {
@@ -106,6 +110,53 @@ __device__ __forceinline__ void self_imag(Cx<double> &a, double g) {
         : "v"(g));
 }
 
+// The same pair update with both coefficients negated when NEG, through the
+// FMA's source negation modifiers (no extra instruction).
+template <bool IMAG, bool NEG>
+__device__ __forceinline__ void pair_s(Cx<float> &a, Cx<float> &b, float ga, float gb) {
+    if constexpr (!IMAG && !NEG) {
+        pair_real(a, b, ga, gb);
+    } else if constexpr (!IMAG && NEG) {
+        asm("v_fma_f32 %0, -%4, %2, %0\n\t"
+            "v_fma_f32 %1, -%4, %3, %1\n\t"
+            "v_fma_f32 %2, -%5, %0, %2\n\t"
+            "v_fma_f32 %3, -%5, %1, %3"
+            : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
+            : "v"(ga), "v"(gb));
+    } else if constexpr (IMAG && !NEG) {
+        pair_imag(a, b, ga, gb);
+    } else {
+        asm("v_fma_f32 %0, %4, %3, %0\n\t"
+            "v_fma_f32 %1, -%4, %2, %1\n\t"
+            "v_fma_f32 %2, %5, %1, %2\n\t"
+            "v_fma_f32 %3, -%5, %0, %3"
+            : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
+            : "v"(ga), "v"(gb));
+    }
+}
+template <bool IMAG, bool NEG>
+__device__ __forceinline__ void pair_s(Cx<double> &a, Cx<double> &b, double ga, double gb) {
+    if constexpr (!IMAG && !NEG) {
+        pair_real(a, b, ga, gb);
+    } else if constexpr (!IMAG && NEG) {
+        asm("v_fma_f64 %0, -%4, %2, %0\n\t"
+            "v_fma_f64 %1, -%4, %3, %1\n\t"
+            "v_fma_f64 %2, -%5, %0, %2\n\t"
+            "v_fma_f64 %3, -%5, %1, %3"
+            : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
+            : "v"(ga), "v"(gb));
+    } else if constexpr (IMAG && !NEG) {
+        pair_imag(a, b, ga, gb);
+    } else {
+        asm("v_fma_f64 %0, %4, %3, %0\n\t"
+            "v_fma_f64 %1, -%4, %2, %1\n\t"
+            "v_fma_f64 %2, %5, %1, %2\n\t"
+            "v_fma_f64 %3, -%5, %0, %3"
+            : "+v"(a.re), "+v"(a.im), "+v"(b.re), "+v"(b.im)
+            : "v"(ga), "v"(gb));
+    }
+}
+
 // Sign masks S[v] = parity(v & zeta) << 31 for all coset labels v, built
 // incrementally (one XOR per label).
 template <int M>
@@ -136,6 +187,27 @@ __device__ __forceinline__ void rot_slot(Cx<T> (&amp)[1 << M], T ga, T gb, uint3
     }
 }
 
+// Static-sign form for ranks up to kStaticSignRank.  Pair (v, w = v | 2^I)
+// takes ga s_w and gb s_v, s_u = s0 (-1)^parity(u & zeta).  With ga
+// pre-multiplied by (-1)^zeta_I (a uniform flip), both become s0 times
+// (-1)^parity(c(v) & zp), c(v) being v with bit I removed and zp zeta with
+// bit I removed: for each of the 2^(M-1) values of zp the signs are
+// compile-time constants and go into negation modifiers.
+__host__ __device__ constexpr int drop_bit(int v, int I) {
+    return ((v >> (I + 1)) << I) | (v & ((1 << I) - 1));
+}
+
+template <typename T, int M, int I, bool IMAG, int ZP, int V = 0>
+__device__ __forceinline__ void rot_fixed(Cx<T> (&amp)[1 << M], T ga, T gb) {
+    if constexpr (V < (1 << M)) {
+        if constexpr (!(V & (1 << I))) {
+            constexpr bool neg = (__builtin_popcount(drop_bit(V, I) & ZP) & 1) != 0;
+            pair_s<IMAG, neg>(amp[V], amp[V | (1 << I)], ga, gb);
+        }
+        rot_fixed<T, M, I, IMAG, ZP, V + 1>(amp, ga, gb);
+    }
+}
+
 // x = 0: new = psi (1 + i tan(phi) sigma) (tau is imaginary).
 template <typename T, int M>
 __device__ __forceinline__ void rot_diag(Cx<T> (&amp)[1 << M], T g, uint32_t zeta) {
@@ -162,20 +234,59 @@ __device__ __forceinline__ void rot_slot_any(Cx<T> (&amp)[1 << M], T ga, T gb, u
         rot_slot<T, M, I, false>(amp, ga, gb, zeta);
 }
 
+// Binary dispatch of a static-sign rotation on the uniform variant index
+// var = slot 2^M + imag 2^(M-1) + zp in [LO, HI); var = M 2^M is the
+// diagonal (x = 0) rotation.
+template <typename T, int M, int LO, int HI>
+__device__ __forceinline__ void rot_var(Cx<T> (&amp)[1 << M], T ga, T gb, uint32_t var,
+                                        uint32_t zeta) {
+    if constexpr (HI - LO == 1) {
+        if constexpr (LO == (M << M)) {
+            rot_diag<T, M>(amp, ga, zeta);
+        } else {
+            constexpr int I = LO >> M;
+            constexpr bool IMAG = ((LO >> (M - 1)) & 1) != 0;
+            constexpr int ZP = LO & ((1 << (M - 1)) - 1);
+            rot_fixed<T, M, I, IMAG, ZP>(amp, ga, gb);
+        }
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (var < (uint32_t)MID)
+            rot_var<T, M, LO, MID>(amp, ga, gb, var, zeta);
+        else
+            rot_var<T, M, MID, HI>(amp, ga, gb, var, zeta);
+    }
+}
+
 // Applies rotations [0, count) of `rots` to the thread's coset.
-// k0: coset representative in the frame of rec.z; tbase: the tile index
-// whose parity with rec.zhigh adds to the sign (0 for span passes).
-template <typename T, int M>
-__device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], uint64_t k0, uint64_t tbase,
+// k0: coset representative in the frame of rec.z (32-bit in a tile frame);
+// tbase: the tile index whose parity with rec.zhigh adds to the sign (0 for
+// span passes).
+template <typename T, int M, typename K0>
+__device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t tbase,
                                            const RotRec<T> *__restrict__ rots, uint32_t count) {
     for (uint32_t r = 0; r < count; ++r) {
         const RotRec<T> rec = rots[r];
-        const uint32_t s0 = parity64(k0 & rec.z) ^ parity64(tbase & rec.zhigh);
-        const T ga = pin(flip(rec.tau_a, s0));
-        const T gb = pin(flip(rec.tau_b, s0));
         const uint32_t slot = rec.info & 15u;
         const bool imag = (rec.info >> 4) & 1u;
         const uint32_t zeta = (rec.info >> 8) & 0xffu;
+        // uniform part of the sign, then one AND and one count per lane
+        const uint32_t tpar = (uint32_t)__builtin_popcountll(tbase & rec.zhigh);
+        uint32_t s0;
+        if constexpr (sizeof(K0) == 4)
+            s0 = ((uint32_t)__builtin_popcount(k0 & (uint32_t)rec.z) + tpar) & 1u;
+        else
+            s0 = ((uint32_t)__builtin_popcountll(k0 & rec.z) + tpar) & 1u;
+        if constexpr (M <= kStaticSignRank) {
+            // tau_a arrives multiplied by (-1)^zeta_slot: both pair
+            // coefficients then share the pattern (-1)^parity(c(v) & zp)
+            const T ga = pin(flip(rec.tau_a, s0));
+            const T gb = pin(flip(rec.tau_b, s0));
+            rot_var<T, M, 0, (M << M) + 1>(amp, ga, gb, (rec.info >> 16) & 0xffu, zeta);
+            continue;
+        }
+        const T ga = pin(flip(rec.tau_a, s0));
+        const T gb = pin(flip(rec.tau_b, s0));
         // one uniform branch per slot, each updating amp in place
         if (slot == 0) rot_slot_any<T, M, 0>(amp, ga, gb, zeta, imag);
         if constexpr (M > 1) if (slot == 1) rot_slot_any<T, M, 1>(amp, ga, gb, zeta, imag);

@@ -49,7 +49,9 @@ prx_status hip_fail(hipError_t e, const char *what);
 //            contributed by the workgroup's base tile
 //   info   : bits 0-3  basis slot of x in the chunk (15 = diagonal, x = 0)
 //            bit  4    tau is imaginary (nY + 1 odd)
+//            bit  5    static-sign variant (chunk rank <= kStaticSignRank)
 //            bits 8-15 zeta: bit i = parity(basis_i & z)
+//            bits 16-23 variant index (static-sign chunks)
 //   tau_a, tau_b : signed magnitudes (real or imaginary parts); for x = 0
 //            only tau_a is used (tan(phi))
 template <typename T>
@@ -63,23 +65,35 @@ struct RotRec {
 };
 
 static constexpr uint32_t kSlotDiag = 15;
+// Chunks of rank up to kStaticSignRank run one compiled variant per
+// (slot, imag, sign pattern); their records carry the variant index in
+// info bits 16..23 and tau_a multiplied by (-1)^zeta_slot.
+static constexpr int kStaticSignRank = 4;
 static constexpr int kMaxChunkRank = 6;
 // Virtual qubits of a tile pass: at most 8 XOR masks of tile-index bits, and
 // at least 16 contiguous amplitudes per tile (128 B at complex64).
 static constexpr int kMaxVirtual = 8;
 static constexpr int kMinTileLow = 4;
 
+// Most threads of a tile workgroup (2^(B - m) <= 2^8).
+static constexpr int kMaxTileThreadBits = 8;
+
 // A chunk of a tile pass: up to kMaxChunkRank basis directions in the
-// workgroup-local frame, with their pivot bits (reduced echelon form,
-// ascending) used to enumerate coset representatives, and a run of
-// rotations whose x masks are basis directions (or zero).
+// workgroup-local frame and a run of rotations whose x masks are basis
+// directions (or zero).  Thread t holds the coset k0(t) XOR span(basis),
+// k0(t) = XOR of cvec[i] over the bits i set in t; the cvec span a
+// complement of the basis span, and the first ones have independent low
+// bits so that the lanes of one LDS access cycle use distinct banks.
 struct ChunkRec {
     uint32_t rot_begin;
     uint32_t rot_count;
     uint32_t basis[kMaxChunkRank];
-    uint8_t pivot[kMaxChunkRank];
-    uint8_t pad[2];
+    uint16_t cvec[kMaxTileThreadBits];
     double fscale[kMaxChunkRank];  // pending per-slot factors K at the chunk's end
+    // element v's factor, the product of fscale over the bits set in v
+    // (v < 2^m, m <= 5), in each state precision
+    float facf[32];
+    double facd[32];
 };
 
 // Longest run of rotations in one chunk (bounds the pending factors: with
@@ -98,6 +112,10 @@ struct SpanArgs {
 
 // Kernel arguments of a tile pass.
 struct TileArgs {
+    // Slot s = tid + u NT of the tile-set holds amplitude
+    // ((t ^ vc(tid >> b)) << b | (tid & (2^b - 1))) ^ uoff[u], with vc(v) the
+    // XOR of the virtual masks selected by v's bits.
+    uint64_t uoff[32];  // 2^m entries (tile chunk rank m <= 5)
     uint64_t vmask[kMaxVirtual];  // virtual masks (tile-index space): tile v of a workgroup's
                                   // set is t XOR (the masks selected by the bits of v)
     uint8_t tpivot[kMaxVirtual];  // pivot bits of the masks' echelon form, ascending

@@ -157,60 +157,76 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
                                                       double *__restrict__ norm_out) {
     constexpr int NT = 1 << (B - M);  // threads
     constexpr int PER = 1 << M;       // amplitudes per thread (tile-set 2^B)
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    Cx<T> *lds = reinterpret_cast<Cx<T> *>(lds_raw);
-    __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
-    __shared__ uint64_t vtab[1 << kMaxVirtual];  // tile-index offset of each tile of the set
+    static_assert(PER <= 32 && B - M <= kMaxTileThreadBits, "tile shape");
+    // The tile-set is the only LDS allocation (2^B amplitudes), so that
+    // 160 KB holds five 12-qubit complex64 workgroups per CU.
+    // static allocation: its address is a link-time constant, so LDS
+    // addresses are plain byte offsets
+    __shared__ __align__(16) Cx<T> lds[1 << B];
+    unsigned char *lds_raw = reinterpret_cast<unsigned char *>(lds);
     const uint32_t tid = threadIdx.x;
 
     uint64_t tb = blockIdx.x;
     for (int i = 0; i < a.g; ++i) tb = insert_zero64(tb, a.tpivot[i]);
-    const int b = a.b;
-    const uint32_t low = (1u << b) - 1u;
-    for (uint32_t v = tid; v < (1u << a.g); v += NT) {
-        uint64_t c = 0;
+    // Tile v of the set has tile index t ^ vc(v), vc(v) = XOR of the masks
+    // selected by v's bits.  Slot s = tid + u NT = tid | u << (B - M) lies in
+    // tile s >> b = (tid >> b) | ((u NT) >> b) (disjoint bits), so its global
+    // index splits into a per-thread part and the host's uniform uoff[u].
+    uint64_t base;
+    {
+        const int b = a.b;
+        uint64_t c = tb;
+        const uint32_t v = tid >> b;
         for (int i = 0; i < a.g; ++i)
             if (v >> i & 1) c ^= a.vmask[i];
-        vtab[v] = c;
+        base = (c << b) | (tid & ((1u << b) - 1u));
     }
-    __syncthreads();
 
-    // LDS slot s = (v << b) | offset holds amplitude ((t ^ vtab[v]) << b) | offset.
     // Every thread issues all its loads before the first LDS store.
     {
         Cx<T> r[PER];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t s = tid + (uint32_t)u * NT;
-            r[u] = psi[((tb ^ vtab[s >> b]) << b) | (s & low)];
-        }
+        for (int u = 0; u < PER; ++u) r[u] = psi[base ^ a.uoff[u]];
 #pragma unroll
         for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
     }
     __syncthreads();
 
+    // all-ones masks of the thread index bits: a chunk's representative is
+    // then one AND-XOR per bit
+    uint32_t tmask[B - M];
+#pragma unroll
+    for (int i = 0; i < B - M; ++i) tmask[i] = pin(0u - ((tid >> i) & 1u));
+    // LDS byte offsets: the XOR of indices commutes with the element shift
+    constexpr uint32_t SH = sizeof(Cx<T>) == 8 ? 3u : 4u;
+
     for (uint32_t c = 0; c < a.chunk_count; ++c) {
         const ChunkRec ch = chunks[a.chunk_begin + c];
-        uint32_t k0 = tid;
+        uint32_t k0 = 0;
 #pragma unroll
-        for (int i = 0; i < M; ++i) k0 = insert_zero32(k0, ch.pivot[i]);
-        uint32_t X[1 << M];
-        X[0] = 0;
+        for (int i = 0; i < B - M; ++i) k0 ^= tmask[i] & ch.cvec[i];
+        const uint32_t k0b = k0 << SH;
+        uint32_t Xb[1 << M];
+        Xb[0] = 0;
 #pragma unroll
-        for (int v = 1; v < (1 << M); ++v) X[v] = X[v & (v - 1)] ^ ch.basis[__builtin_ctz(v)];
+        for (int v = 1; v < (1 << M); ++v)
+            Xb[v] = Xb[v & (v - 1)] ^ (ch.basis[__builtin_ctz(v)] << SH);
         Cx<T> amp[1 << M];
 #pragma unroll
-        for (int v = 0; v < (1 << M); ++v) amp[v] = lds[k0 ^ X[v]];
+        for (int v = 0; v < (1 << M); ++v)
+            amp[v] = *reinterpret_cast<const Cx<T> *>(lds_raw + (k0b ^ Xb[v]));
         apply_rots<T, M>(amp, k0, tb, rots + ch.rot_begin, ch.rot_count);
-        double F[1 << M];
-        pending_factors<M>(F, ch.fscale);
 #pragma unroll
         for (int v = 0; v < (1 << M); ++v) {
-            const T f = (T)F[v];
+            T f;
+            if constexpr (sizeof(T) == 4)
+                f = ch.facf[v];
+            else
+                f = ch.facd[v];
             Cx<T> o;
             o.re = amp[v].re * f;
             o.im = amp[v].im * f;
-            lds[k0 ^ X[v]] = o;
+            *reinterpret_cast<Cx<T> *>(lds_raw + (k0b ^ Xb[v])) = o;
         }
         __syncthreads();
     }
@@ -225,16 +241,16 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
         for (int u = 0; u < PER; ++u) r[u] = lds[tid + (uint32_t)u * NT];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-            const uint32_t sl = tid + (uint32_t)u * NT;
             Cx<T> o = r[u];
             o.re *= s;
             o.im *= s;
-            psi[((tb ^ vtab[sl >> b]) << b) | (sl & low)] = o;
+            psi[base ^ a.uoff[u]] = o;
             nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
         }
     }
     if (norm_out) {
-        nrm = block_sum<NT>(nrm, red);
+        __syncthreads();  // the tile-set's LDS is reused for the partial sums
+        nrm = block_sum<NT>(nrm, reinterpret_cast<double *>(lds_raw));
         if (tid == 0) norm_out[blockIdx.x] = nrm;
     }
 }
@@ -431,17 +447,9 @@ template <typename T, int B, int M>
 static hipError_t tile_launch_one(void *psi, const TileArgs &a, const void *rots,
                                   const ChunkRec *chunks, const double *rin, double *nout,
                                   hipStream_t s, unsigned *blocks) {
-    const size_t lds = sizeof(Cx<T>) << B;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_tile<T, B, M>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
     const unsigned nb = tile_blocks(a.n, B);
     *blocks = nb;
-    hipLaunchKernelGGL((k_tile<T, B, M>), dim3(nb), dim3(1 << (B - M)), lds, s, (Cx<T> *)psi, a,
+    hipLaunchKernelGGL((k_tile<T, B, M>), dim3(nb), dim3(1 << (B - M)), 0, s, (Cx<T> *)psi, a,
                        (const RotRec<T> *)rots, chunks, rin, nout);
     return hipGetLastError();
 }

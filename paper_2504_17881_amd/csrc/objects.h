@@ -33,6 +33,7 @@ struct RotRecD {
     uint64_t z = 0, zhigh = 0;
     uint32_t info = 0;
     double tau_a = 0.0, tau_b = 0.0;
+    bool fold = false;  // device tau_a is -tau_a (static-sign variant with zeta_slot set)
 };
 
 enum PassKind { kPlain = 0, kSpan = 1, kTile = 2 };

@@ -107,13 +107,24 @@ static Coef fused_coef(const KRot &r) {
 // updates the slot's factor.
 struct SlotScale {
     double K[kMaxChunkRank] = {1, 1, 1, 1, 1, 1};
+    // m: the chunk's rank (the kernel's coset size 2^m).
     RotRecD record(const KRot &k, uint32_t slot, uint32_t zeta, uint64_t zframe,
-                   uint64_t zhigh) {
+                   uint64_t zhigh, int m) {
         const Coef cf = fused_coef(k);
         RotRecD rr;
         rr.z = zframe;
         rr.zhigh = zhigh;
         rr.info = slot | (cf.imag << 4) | (zeta << 8);
+        if (m <= kStaticSignRank) {
+            uint32_t var = (uint32_t)m << m;  // diagonal
+            if (slot != kSlotDiag) {
+                const uint32_t zp = (((zeta >> (slot + 1)) << slot) | (zeta & ((1u << slot) - 1u))) &
+                                    ((1u << (m - 1)) - 1u);
+                var = (slot << m) | (cf.imag << (m - 1)) | zp;
+                rr.fold = ((zeta >> slot) & 1u) != 0;
+            }
+            rr.info |= (var << 16) | (1u << 5);
+        }
         if (slot == kSlotDiag) {
             rr.tau_a = cf.tau;
             rr.tau_b = 0.0;
@@ -144,6 +155,36 @@ static PlainArgs plain_args(int n, const KRot &r) {
 }
 
 // ---------------------------------------------------------------- planner
+
+// Coset representatives of a tile chunk: thread t holds k0(t) XOR span(basis)
+// with k0(t) = XOR of cvec[i] over the bits i of t, so the cvec must span a
+// complement of the basis span (B - m vectors).  LDS serves one access cycle
+// for 2^bank_bits consecutive lanes (32 lanes of 8-byte, 16 lanes of 16-byte
+// elements); those lanes hit distinct banks when the low bank_bits bits of
+// cvec[0 .. bank_bits-1] are independent, so cvec[i] = e_i XOR h with the
+// smallest high part h that keeps the set independent (always possible for
+// rank m below B - bank_bits), then unit vectors complete the complement.
+static void chunk_complement(const Gf2 &basis_span, int B, int nbits, int bank_bits,
+                             uint16_t *cvec) {
+    Gf2 G = basis_span;
+    int t = 0;
+    for (int i = 0; i < bank_bits && i < B && t < nbits; ++i) {
+        for (uint32_t h = 0; h < (1u << (B - bank_bits)); ++h) {
+            const uint32_t c = (1u << i) ^ (h << bank_bits);
+            if (!G.contains(c)) {
+                G.add(c);
+                cvec[t++] = (uint16_t)c;
+                break;
+            }
+        }
+    }
+    for (int u = 0; u < B && t < nbits; ++u) {
+        if (!G.contains(1ull << u)) {
+            G.add(1ull << u);
+            cvec[t++] = (uint16_t)(1u << u);
+        }
+    }
+}
 
 struct Builder {
     prx_plan &P;
@@ -269,7 +310,7 @@ struct Builder {
             if (k.x) slot = (uint32_t)(std::find(basis.begin(), basis.end(), k.x) - basis.begin());
             uint32_t zeta = 0;
             for (int i = 0; i < ps.m; ++i) zeta |= par(basis[i] & k.z) << i;
-            recs.push_back(ss.record(k, slot, zeta, k.z, 0));
+            recs.push_back(ss.record(k, slot, zeta, k.z, 0, ps.m));
         }
         for (int i = 0; i < kMaxChunkRank; ++i) ps.fscale[i] = ss.K[i];
         ps.scale = scale;
@@ -356,11 +397,8 @@ struct Builder {
             std::memset(&ch, 0, sizeof(ch));
             ch.rot_begin = (uint32_t)r;
             ch.rot_count = (uint32_t)(q - r);
-            auto piv = cg.pivots();
-            for (int i = 0; i < cfg.m; ++i) {
-                ch.basis[i] = basis[i];
-                ch.pivot[i] = (uint8_t)piv[i];
-            }
+            for (int i = 0; i < cfg.m; ++i) ch.basis[i] = basis[i];
+            chunk_complement(cg, cfg.B, cfg.B - cfg.m, P.dtype == PRX_C64 ? 5 : 4, ch.cvec);
             P.chunks.push_back(ch);
             SlotScale ss;
             for (size_t t = r; t < q; ++t) {
@@ -371,9 +409,17 @@ struct Builder {
                 if (L.x) slot = (uint32_t)(std::find(basis.begin(), basis.end(), L.x) - basis.begin());
                 uint32_t zeta = 0;
                 for (int i = 0; i < cfg.m; ++i) zeta |= par((uint64_t)basis[i] & L.z) << i;
-                recs.push_back(ss.record(k, slot, zeta, L.z, L.zhigh));
+                recs.push_back(ss.record(k, slot, zeta, L.z, L.zhigh, cfg.m));
             }
-            for (int i = 0; i < kMaxChunkRank; ++i) P.chunks.back().fscale[i] = ss.K[i];
+            ChunkRec &cb = P.chunks.back();
+            for (int i = 0; i < kMaxChunkRank; ++i) cb.fscale[i] = ss.K[i];
+            for (int v = 0; v < (1 << cfg.m) && v < 32; ++v) {
+                double f = 1.0;
+                for (int i = 0; i < cfg.m; ++i)
+                    if (v >> i & 1) f *= ss.K[i];
+                cb.facd[v] = f;
+                cb.facf[v] = (float)f;
+            }
             r = q;
         }
         ps.c1 = P.chunks.size();
@@ -532,7 +578,7 @@ static void pack_records(prx_plan &P, const std::vector<RotRecD> &recs) {
         r.z = recs[i].z;
         r.zhigh = recs[i].zhigh;
         r.info = recs[i].info;
-        r.tau_a = (T)recs[i].tau_a;
+        r.tau_a = (T)(recs[i].fold ? -recs[i].tau_a : recs[i].tau_a);
         r.tau_b = (T)recs[i].tau_b;
         out[i] = r;
     }
@@ -742,6 +788,15 @@ static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws
                 a.vmask[k] = ps.vmask[k];
                 a.tpivot[k] = (uint8_t)ps.tpivot[k];
             }
+            // slot u NT of the tile-set: tile (u NT) >> b, offset (u NT) mod 2^b
+            const uint32_t nt = 1u << (ps.B - ps.m);
+            for (uint32_t u = 0; u < (1u << ps.m); ++u) {
+                const uint32_t v = (u * nt) >> ps.b;
+                uint64_t c = 0;
+                for (int k = 0; k < ps.g; ++k)
+                    if (v >> k & 1) c ^= ps.vmask[k];
+                a.uoff[u] = (c << ps.b) | ((u * nt) & ((1u << ps.b) - 1u));
+            }
             a.n = P->n;
             a.b = ps.b;
             a.g = ps.g;
@@ -836,10 +891,8 @@ prx_status prx_plan_chunk(const prx_plan *P, size_t i, prx_chunk_info *o) {
     if (i >= P->chunks.size()) return fail(PRX_ERR_INVALID, "chunk index out of range");
     const ChunkRec &c = P->chunks[i];
     std::memset(o, 0, sizeof(*o));
-    for (int k = 0; k < kMaxChunkRank; ++k) {
-        o->basis[k] = c.basis[k];
-        o->pivot[k] = c.pivot[k];
-    }
+    for (int k = 0; k < kMaxChunkRank; ++k) o->basis[k] = c.basis[k];
+    for (int k = 0; k < kMaxTileThreadBits; ++k) o->cvec[k] = c.cvec[k];
     for (int k = 0; k < kMaxChunkRank; ++k) o->fscale[k] = c.fscale[k];
     o->rot_begin = c.rot_begin;
     o->rot_count = c.rot_count;
@@ -862,6 +915,8 @@ prx_status prx_plan_rotation(const prx_plan *P, size_t i, prx_rot_info *o) {
         o->slot = r.info & 15u;
         o->imag = (r.info >> 4) & 1u;
         o->zeta = (r.info >> 8) & 0xffu;
+        o->var = (r.info >> 16) & 0xffu;
+        o->static_sign = (r.info >> 5) & 1u;
         o->tau = r.tau_a;
         o->tau_b = r.tau_b;
     } else {
@@ -871,6 +926,8 @@ prx_status prx_plan_rotation(const prx_plan *P, size_t i, prx_rot_info *o) {
         o->slot = r.info & 15u;
         o->imag = (r.info >> 4) & 1u;
         o->zeta = (r.info >> 8) & 0xffu;
+        o->var = (r.info >> 16) & 0xffu;
+        o->static_sign = (r.info >> 5) & 1u;
         o->tau = r.tau_a;
         o->tau_b = r.tau_b;
     }

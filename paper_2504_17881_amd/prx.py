@@ -80,7 +80,7 @@ class prx_pass_info(ctypes.Structure):
 
 
 class prx_chunk_info(ctypes.Structure):
-    _fields_ = [("basis", ctypes.c_uint32 * 6), ("pivot", ctypes.c_uint32 * 6),
+    _fields_ = [("basis", ctypes.c_uint32 * 6), ("cvec", ctypes.c_uint32 * 8),
                 ("fscale", ctypes.c_double * 6), ("rot_begin", _sz), ("rot_count", _sz)]
 
 
@@ -88,7 +88,9 @@ class prx_rot_info(ctypes.Structure):
     _fields_ = [("x", ctypes.c_uint64), ("z", ctypes.c_uint64), ("phi", ctypes.c_double),
                 ("source", _sz), ("zframe", ctypes.c_uint64), ("zhigh", ctypes.c_uint64),
                 ("slot", ctypes.c_uint32), ("imag", ctypes.c_uint32),
-                ("zeta", ctypes.c_uint32), ("tau", ctypes.c_double), ("tau_b", ctypes.c_double)]
+                ("zeta", ctypes.c_uint32), ("var", ctypes.c_uint32),
+                ("static_sign", ctypes.c_uint32), ("tau", ctypes.c_double),
+                ("tau_b", ctypes.c_double)]
 
 
 def _sig(name, res, *args):
@@ -350,7 +352,7 @@ def prx_plan_chunk(plan: int, i: int) -> dict:
     _check(_lib.prx_plan_chunk(plan, i, ctypes.byref(o)))
     d = {f: getattr(o, f) for f, _ in prx_chunk_info._fields_}
     d["basis"] = list(d["basis"])
-    d["pivot"] = list(d["pivot"])
+    d["cvec"] = list(d["cvec"])
     d["fscale"] = list(d["fscale"])
     return d
 

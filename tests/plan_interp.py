@@ -50,6 +50,23 @@ def _apply_records(amp, recs, s0_of, m):
         unit = 1j if r["imag"] else 1.0
         zeta = r["zeta"]
         slot = r["slot"]
+        if r["static_sign"] and slot != 15:
+            # compiled variant: var = slot 2^m + imag 2^(m-1) + zp, tau_a
+            # stored times (-1)^zeta_slot, pair sign (-1)^parity(c(v) & zp)
+            var = r["var"]
+            I, imag, zp = var >> m, (var >> (m - 1)) & 1, var & ((1 << (m - 1)) - 1)
+            drop = lambda u: ((u >> (I + 1)) << I) | (u & ((1 << I) - 1))  # noqa: E731
+            assert I == slot and imag == r["imag"] and zp == drop(zeta)
+            for v in range(1 << m):
+                if v >> I & 1:
+                    continue
+                w = v | (1 << I)
+                sg = 1.0 - 2.0 * (bin(drop(v) & zp).count("1") & 1)
+                amp[v] = amp[v] + unit * ga * sg * amp[w]
+                amp[w] = amp[w] + unit * gb * sg * amp[v]
+            continue
+        if r["static_sign"]:
+            assert r["var"] == m << m
         if slot == 15:
             for v in range(1 << m):
                 sv = 1.0 - 2.0 * (bin(v & zeta).count("1") & 1)
@@ -124,9 +141,11 @@ def run_plan(plan: int, psi0: np.ndarray, n: int) -> np.ndarray:
             lds = psi[gidx]
             for c in range(ps["chunk_begin"], ps["chunk_begin"] + ps["chunk_count"]):
                 ch = P.prx_plan_chunk(plan, c)
-                k0 = _insert_zeros(np.arange(1 << (B - m), dtype=np.uint64), ch["pivot"][:m])
+                k0 = np.asarray(_xcomb(ch["cvec"][:B - m], B - m), dtype=np.uint64)  # per thread
                 X = _xcomb(ch["basis"][:m], m)
                 idx = [k0 ^ np.uint64(X[v]) for v in range(1 << m)]
+                # the threads' cosets partition the tile-set
+                assert np.array_equal(np.sort(np.concatenate(idx)), np.arange(1 << B))
                 amp = [lds[:, i.astype(np.int64)] for i in idx]
                 crecs = rots[ch["rot_begin"]:ch["rot_begin"] + ch["rot_count"]]
 

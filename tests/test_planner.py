@@ -162,3 +162,41 @@ def test_sub_range_plans_compose():
     for p in (a, b):
         P.prx_plan_destroy(p)
     P.prx_sched_destroy(s)
+
+
+@pytest.mark.parametrize("dtype,bank_bits", [(P.PRX_C64, 5), (P.PRX_C128, 4)])
+def test_chunk_lanes_hit_distinct_lds_banks(dtype, bank_bits):
+    """Every tile chunk's coset representatives give the lanes of one LDS
+    access cycle (2^bank_bits consecutive threads) distinct low index bits,
+    and the cosets of all threads partition the tile-set."""
+    n = 20
+    x, z, h = synth.jw_hamiltonian(n, 400, 5)
+    H = P.prx_ham_create(n, x, z, h)
+    s = P.prx_sched_trotter(H, 1, 1.0, 1, P.PRX_REORDER_SUFFIX)
+    _, rx, _, _ = P.prx_sched_view(s)
+    pl = P.prx_plan_create(s, n, dtype, 0, len(rx), P.PRX_FUSED, dict(span_max=2))
+    info = P.prx_plan_get_info(pl)
+    checked = 0
+    for pi in range(info["passes"]):
+        ps = P.prx_plan_pass(pl, pi)
+        if ps["kind"] != 2:
+            continue
+        B, m = ps["B"], ps["m"]
+        for c in range(ps["chunk_begin"], ps["chunk_begin"] + ps["chunk_count"]):
+            cv = P.prx_plan_chunk(pl, c)["cvec"][:B - m]
+            k0 = [0] * (1 << (B - m))
+            for t in range(1, 1 << (B - m)):
+                low = (t & -t).bit_length() - 1
+                k0[t] = k0[t & (t - 1)] ^ cv[low]
+            span = {0}
+            for bv in P.prx_plan_chunk(pl, c)["basis"][:m]:
+                span |= {q ^ bv for q in span}
+            assert len({k ^ q for k in k0 for q in span}) == 1 << B
+            g = 1 << bank_bits
+            for base in range(0, len(k0), g):
+                assert len({k % g for k in k0[base:base + g]}) == g
+            checked += 1
+    assert checked > 0
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
