@@ -225,7 +225,7 @@ typedef struct {
  * of the basis span). */
 typedef struct {
     uint32_t basis[6];
-    uint32_t cvec[8];
+    uint32_t cvec[9];
     double fscale[6];                 /* pending per-slot factors at the chunk's end */
     size_t rot_begin, rot_count;
 } prx_chunk_info;

@@ -75,8 +75,8 @@ static constexpr int kMaxChunkRank = 6;
 static constexpr int kMaxVirtual = 8;
 static constexpr int kMinTileLow = 4;
 
-// Most threads of a tile workgroup (2^(B - m) <= 2^8).
-static constexpr int kMaxTileThreadBits = 8;
+// Most threads of a tile workgroup (2^(B - m) <= 2^9).
+static constexpr int kMaxTileThreadBits = 9;
 
 // A chunk of a tile pass: up to kMaxChunkRank basis directions in the
 // workgroup-local frame and a run of rotations whose x masks are basis

@@ -434,7 +434,7 @@ hipError_t launch_span(prx_dtype dt, int m, void *psi, const SpanArgs &a, const 
 }
 
 // (B, M) pairs instantiated for the tile kernel.
-#define PRX_TILE_SHAPES(X) X(10, 3) X(10, 4) X(11, 4) X(12, 4) X(12, 5) X(13, 5)
+#define PRX_TILE_SHAPES(X) X(10, 3) X(10, 4) X(11, 4) X(12, 4) X(12, 5) X(13, 4) X(13, 5)
 
 bool tile_supported(prx_dtype dt, int B, int m) {
 #define PRX_TS(BB, MM) if (B == BB && m == MM) return dt == PRX_C64 || BB <= 12;

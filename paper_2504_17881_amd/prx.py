@@ -80,7 +80,7 @@ class prx_pass_info(ctypes.Structure):
 
 
 class prx_chunk_info(ctypes.Structure):
-    _fields_ = [("basis", ctypes.c_uint32 * 6), ("cvec", ctypes.c_uint32 * 8),
+    _fields_ = [("basis", ctypes.c_uint32 * 6), ("cvec", ctypes.c_uint32 * 9),
                 ("fscale", ctypes.c_double * 6), ("rot_begin", _sz), ("rot_count", _sz)]
 
 

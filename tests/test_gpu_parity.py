@@ -68,6 +68,7 @@ SHAPES = [
     dict(tile_qubits=11, chunk_rank=4, max_virtual=1),
     dict(tile_qubits=12, chunk_rank=4, max_virtual=2),
     dict(tile_qubits=12, chunk_rank=5),
+    dict(tile_qubits=13, chunk_rank=4, max_virtual=2, span_max=2),
     dict(tile_qubits=10, chunk_rank=4, max_virtual=5, span_max=2),
     dict(tile_qubits=11, chunk_rank=4, max_virtual=4, span_max=2),
     dict(span_max=1),
