@@ -149,7 +149,7 @@ typedef struct {
     int chunk_rank;      /* rotations' X-span rank a thread holds in registers (default 4) */
     int max_fuse;        /* max rotations per tile pass (default 128) */
     int span_max;        /* max rotations per span pass (default: chunk_rank and repeats) */
-    int max_virtual;     /* max high-qubit XOR masks gathered into a tile, <= 8; the tile
+    int max_virtual;     /* max high-qubit XOR masks gathered into a tile, <= 10; the tile
                             keeps at least 16 contiguous amplitudes (default 8) */
     int renorm_every;    /* C64: renormalise in FP64 every k passes (default 1; -1 = never) */
     int commuting;       /* 1: planner may swap adjacent commuting rotations (default 0) */
@@ -212,8 +212,8 @@ typedef struct {
     int B, b, g, m;                   /* tile qubits, low qubits, virtual qubits, rank */
     uint64_t basis[6];                /* span: X-mask basis (global frame) */
     uint32_t pivot[6];                /* span: ascending pivot bits of its echelon form */
-    uint64_t vmask[8];                /* tile: virtual masks (tile-index space), g used */
-    uint32_t tpivot[8];               /* tile: ascending pivot bits of their echelon form */
+    uint64_t vmask[10];               /* tile: virtual masks (tile-index space), g used */
+    uint32_t tpivot[10];              /* tile: ascending pivot bits of their echelon form */
     double scale;
     double fscale[6];                 /* span: pending per-slot factors (see prx_rot_info) */
     int norm_out, renorm_in;          /* C64 renormalisation hand-off */
@@ -225,7 +225,7 @@ typedef struct {
  * of the basis span). */
 typedef struct {
     uint32_t basis[6];
-    uint32_t cvec[9];
+    uint32_t cvec[10];
     double fscale[6];                 /* pending per-slot factors at the chunk's end */
     size_t rot_begin, rot_count;
 } prx_chunk_info;

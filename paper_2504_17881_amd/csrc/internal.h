@@ -70,13 +70,13 @@ static constexpr uint32_t kSlotDiag = 15;
 // info bits 16..23 and tau_a multiplied by (-1)^zeta_slot.
 static constexpr int kStaticSignRank = 4;
 static constexpr int kMaxChunkRank = 6;
-// Virtual qubits of a tile pass: at most 8 XOR masks of tile-index bits, and
-// at least 16 contiguous amplitudes per tile (128 B at complex64).
-static constexpr int kMaxVirtual = 8;
+// Virtual qubits of a tile pass: at most 10 XOR masks of tile-index bits,
+// and at least 16 contiguous amplitudes per tile (128 B at complex64).
+static constexpr int kMaxVirtual = 10;
 static constexpr int kMinTileLow = 4;
 
-// Most threads of a tile workgroup (2^(B - m) <= 2^9).
-static constexpr int kMaxTileThreadBits = 9;
+// Most threads of a tile workgroup (2^(B - m) <= 2^10).
+static constexpr int kMaxTileThreadBits = 10;
 
 // A chunk of a tile pass: up to kMaxChunkRank basis directions in the
 // workgroup-local frame and a run of rotations whose x masks are basis
@@ -118,7 +118,8 @@ struct TileArgs {
     uint64_t uoff[32];  // 2^m entries (tile chunk rank m <= 5)
     uint64_t vmask[kMaxVirtual];  // virtual masks (tile-index space): tile v of a workgroup's
                                   // set is t XOR (the masks selected by the bits of v)
-    uint8_t tpivot[kMaxVirtual];  // pivot bits of the masks' echelon form, ascending
+    uint64_t tpivots;             // pivot bits of the masks' echelon form, ascending,
+                                  // 6 bits each (pivot i in bits 6i .. 6i+5)
     int n, b, g;
     uint32_t chunk_begin, chunk_count;
     double scale;

@@ -29,6 +29,8 @@
 // psi'), tau = beta / cos(phi); a pass multiplies its cosines (and an FP64
 // renormalisation factor) into one scale applied at the store.
 
+#include <mutex>
+
 #include "device.h"
 
 namespace prx {
@@ -149,6 +151,16 @@ __global__ void __launch_bounds__(256) k_span(Cx<T> *__restrict__ psi, SpanArgs 
 
 // ------------------------------------------------------------------ tile
 
+// Tile-sets of 13 and 14 qubits (complex64) leave room for one or two
+// workgroups per CU; those run persistently, each workgroup striding over
+// the tile-sets and loading the next one into registers while it computes
+// the current one.  Smaller tile-sets run one workgroup per tile-set, five
+// per CU, which overlaps loads and compute across workgroups.
+template <typename T, int B>
+struct TilePersist {
+    static constexpr bool value = sizeof(T) == 4 && B >= 13;
+};
+
 template <typename T, int B, int M>
 __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, TileArgs a,
                                                       const RotRec<T> *__restrict__ rots,
@@ -157,40 +169,35 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
                                                       double *__restrict__ norm_out) {
     constexpr int NT = 1 << (B - M);  // threads
     constexpr int PER = 1 << M;       // amplitudes per thread (tile-set 2^B)
+    constexpr bool PERSIST = TilePersist<T, B>::value;
     static_assert(PER <= 32 && B - M <= kMaxTileThreadBits, "tile shape");
-    // The tile-set is the only LDS allocation (2^B amplitudes), so that
-    // 160 KB holds five 12-qubit complex64 workgroups per CU.
-    // static allocation: its address is a link-time constant, so LDS
-    // addresses are plain byte offsets
+    // The tile-set is the only LDS allocation (2^B amplitudes): 160 KB hold
+    // five 12-qubit complex64 workgroups per CU.  Static, so that its address
+    // is a link-time constant and LDS addresses are plain byte offsets.
     __shared__ __align__(16) Cx<T> lds[1 << B];
     unsigned char *lds_raw = reinterpret_cast<unsigned char *>(lds);
     const uint32_t tid = threadIdx.x;
+    const uint32_t nsets = (uint32_t)(1ull << (a.n - B));
 
-    uint64_t tb = blockIdx.x;
-    for (int i = 0; i < a.g; ++i) tb = insert_zero64(tb, a.tpivot[i]);
-    // Tile v of the set has tile index t ^ vc(v), vc(v) = XOR of the masks
-    // selected by v's bits.  Slot s = tid + u NT = tid | u << (B - M) lies in
-    // tile s >> b = (tid >> b) | ((u NT) >> b) (disjoint bits), so its global
-    // index splits into a per-thread part and the host's uniform uoff[u].
-    uint64_t base;
-    {
-        const int b = a.b;
-        uint64_t c = tb;
-        const uint32_t v = tid >> b;
+    // Tile v of set w has tile index t(w) ^ vc(v), vc(v) = XOR of the masks
+    // selected by v's bits; t(w) inserts zeros at the masks' pivots.  Slot
+    // s = tid + u NT = tid | u << (B - M) lies in tile s >> b = (tid >> b) |
+    // ((u NT) >> b) (disjoint bits), so its global index splits into a
+    // per-thread part and the host's uniform uoff[u].
+    const uint64_t vt = [&] {
+        uint64_t c = 0;
+        const uint32_t v = tid >> a.b;
         for (int i = 0; i < a.g; ++i)
             if (v >> i & 1) c ^= a.vmask[i];
-        base = (c << b) | (tid & ((1u << b) - 1u));
-    }
-
-    // Every thread issues all its loads before the first LDS store.
-    {
-        Cx<T> r[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) r[u] = psi[base ^ a.uoff[u]];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
-    }
-    __syncthreads();
+        return c;
+    }();
+    // (pivots unpacked with shifts: no indexed load from the argument block)
+    auto tile_of = [&](uint32_t w) {
+        uint64_t t = w;
+        for (int i = 0; i < a.g; ++i) t = insert_zero64(t, (uint32_t)(a.tpivots >> (6 * i)) & 63u);
+        return t;
+    };
+    auto base_of = [&](uint64_t t) { return ((t ^ vt) << a.b) | (tid & ((1u << a.b) - 1u)); };
 
     // all-ones masks of the thread index bits: a chunk's representative is
     // then one AND-XOR per bit
@@ -200,52 +207,92 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
     // LDS byte offsets: the XOR of indices commutes with the element shift
     constexpr uint32_t SH = sizeof(Cx<T>) == 8 ? 3u : 4u;
 
-    for (uint32_t c = 0; c < a.chunk_count; ++c) {
-        const ChunkRec ch = chunks[a.chunk_begin + c];
-        uint32_t k0 = 0;
-#pragma unroll
-        for (int i = 0; i < B - M; ++i) k0 ^= tmask[i] & ch.cvec[i];
-        const uint32_t k0b = k0 << SH;
-        uint32_t Xb[1 << M];
-        Xb[0] = 0;
-#pragma unroll
-        for (int v = 1; v < (1 << M); ++v)
-            Xb[v] = Xb[v & (v - 1)] ^ (ch.basis[__builtin_ctz(v)] << SH);
-        Cx<T> amp[1 << M];
-#pragma unroll
-        for (int v = 0; v < (1 << M); ++v)
-            amp[v] = *reinterpret_cast<const Cx<T> *>(lds_raw + (k0b ^ Xb[v]));
-        apply_rots<T, M>(amp, k0, tb, rots + ch.rot_begin, ch.rot_count);
-#pragma unroll
-        for (int v = 0; v < (1 << M); ++v) {
-            T f;
-            if constexpr (sizeof(T) == 4)
-                f = ch.facf[v];
-            else
-                f = ch.facd[v];
-            Cx<T> o;
-            o.re = amp[v].re * f;
-            o.im = amp[v].im * f;
-            *reinterpret_cast<Cx<T> *>(lds_raw + (k0b ^ Xb[v])) = o;
-        }
-        __syncthreads();
-    }
-
     double sc = a.scale;
     if (renorm_in) sc *= *renorm_in;
     const T s = (T)sc;
     double nrm = 0.0;
-    {
-        Cx<T> r[PER];
+
+    // Set order: persistent workgroups stride over the sets; otherwise the
+    // workgroups, dispatched round-robin over the 8 XCDs, give each XCD a
+    // contiguous range of sets.
+    uint32_t w = blockIdx.x;
+    if (!PERSIST && (gridDim.x & 7u) == 0u)
+        w = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    // Every thread issues all its loads before the first LDS store.  A
+    // persistent workgroup enters each iteration with its set in LDS, loads
+    // the next set into registers, computes and stores the current one, and
+    // only then writes the loaded set to LDS: the loads' wait then sits
+    // behind the stores in the same iteration, and the stores drain while
+    // the next set is computed.
+    Cx<T> r[PER];
+    if (w < nsets) {
+        const uint64_t b0 = base_of(tile_of(w));
 #pragma unroll
-        for (int u = 0; u < PER; ++u) r[u] = lds[tid + (uint32_t)u * NT];
+        for (int u = 0; u < PER; ++u) r[u] = psi[b0 ^ a.uoff[u]];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            Cx<T> o = r[u];
-            o.re *= s;
-            o.im *= s;
-            psi[base ^ a.uoff[u]] = o;
-            nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+        for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
+        __syncthreads();
+    }
+    for (; w < nsets; w += PERSIST ? gridDim.x : nsets) {
+        const uint64_t tb = tile_of(w);
+        const uint64_t base = base_of(tb);
+        const uint32_t wn = w + gridDim.x;
+        const bool next = PERSIST && wn < nsets;
+        if (next) {
+            const uint64_t bn = base_of(tile_of(wn));
+#pragma unroll
+            for (int u = 0; u < PER; ++u) r[u] = psi[bn ^ a.uoff[u]];
+        }
+
+        for (uint32_t c = 0; c < a.chunk_count; ++c) {
+            const ChunkRec ch = chunks[a.chunk_begin + c];
+            uint32_t k0 = 0;
+#pragma unroll
+            for (int i = 0; i < B - M; ++i) k0 ^= tmask[i] & ch.cvec[i];
+            const uint32_t k0b = k0 << SH;
+            uint32_t Xb[1 << M];
+            Xb[0] = 0;
+#pragma unroll
+            for (int v = 1; v < (1 << M); ++v)
+                Xb[v] = Xb[v & (v - 1)] ^ (ch.basis[__builtin_ctz(v)] << SH);
+            Cx<T> amp[1 << M];
+#pragma unroll
+            for (int v = 0; v < (1 << M); ++v)
+                amp[v] = *reinterpret_cast<const Cx<T> *>(lds_raw + (k0b ^ Xb[v]));
+            apply_rots<T, M>(amp, k0, tb, rots + ch.rot_begin, ch.rot_count);
+#pragma unroll
+            for (int v = 0; v < (1 << M); ++v) {
+                T f;
+                if constexpr (sizeof(T) == 4)
+                    f = ch.facf[v];
+                else
+                    f = ch.facd[v];
+                Cx<T> o;
+                o.re = amp[v].re * f;
+                o.im = amp[v].im * f;
+                *reinterpret_cast<Cx<T> *>(lds_raw + (k0b ^ Xb[v])) = o;
+            }
+            __syncthreads();
+        }
+
+        {
+            Cx<T> q[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) q[u] = lds[tid + (uint32_t)u * NT];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                Cx<T> o = q[u];
+                o.re *= s;
+                o.im *= s;
+                psi[base ^ a.uoff[u]] = o;
+                nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+            }
+        }
+        if (next) {
+            __syncthreads();  // every thread has read the finished set
+#pragma unroll
+            for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
+            __syncthreads();
         }
     }
     if (norm_out) {
@@ -406,6 +453,36 @@ hipError_t launch_plain(prx_dtype dt, void *psi, const PlainArgs &a, hipStream_t
 unsigned span_blocks(int n, int m) { return ceil_div_u(1ull << (n - m), 256u); }
 unsigned tile_blocks(int n, int B) { return (unsigned)(1ull << (n - B)); }
 
+// Persistent tile kernels stride over the 2^(n-B) tile-sets with the
+// workgroups that fit on the device at once (cached per device and kernel).
+static unsigned tile_grid(const void *kernel, int n, int B, int threads) {
+    struct Entry {
+        const void *k;
+        int dev;
+        unsigned resident;
+    };
+    static Entry cache[64];
+    static int used = 0;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    unsigned resident = 0;
+    for (int i = 0; i < used; ++i)
+        if (cache[i].k == kernel && cache[i].dev == dev) resident = cache[i].resident;
+    if (!resident) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
+            cus <= 0 || per <= 0)
+            return tile_blocks(n, B);  // one workgroup per tile-set
+        resident = (unsigned)(cus * per);
+        if (used < 64) cache[used++] = Entry{kernel, dev, resident};
+    }
+    const unsigned sets = tile_blocks(n, B);
+    return sets < resident ? sets : resident;
+}
+
 bool span_supported(prx_dtype, int m) { return m >= 1 && m <= 5; }
 
 template <typename T>
@@ -434,7 +511,7 @@ hipError_t launch_span(prx_dtype dt, int m, void *psi, const SpanArgs &a, const 
 }
 
 // (B, M) pairs instantiated for the tile kernel.
-#define PRX_TILE_SHAPES(X) X(10, 3) X(10, 4) X(11, 4) X(12, 4) X(12, 5) X(13, 4) X(13, 5)
+#define PRX_TILE_SHAPES(X) X(10, 3) X(10, 4) X(11, 4) X(12, 4) X(12, 5) X(13, 4) X(13, 5) X(14, 4)
 
 bool tile_supported(prx_dtype dt, int B, int m) {
 #define PRX_TS(BB, MM) if (B == BB && m == MM) return dt == PRX_C64 || BB <= 12;
@@ -447,7 +524,9 @@ template <typename T, int B, int M>
 static hipError_t tile_launch_one(void *psi, const TileArgs &a, const void *rots,
                                   const ChunkRec *chunks, const double *rin, double *nout,
                                   hipStream_t s, unsigned *blocks) {
-    const unsigned nb = tile_blocks(a.n, B);
+    const unsigned nb = TilePersist<T, B>::value
+                            ? tile_grid((const void *)k_tile<T, B, M>, a.n, B, 1 << (B - M))
+                            : tile_blocks(a.n, B);
     *blocks = nb;
     hipLaunchKernelGGL((k_tile<T, B, M>), dim3(nb), dim3(1 << (B - M)), 0, s, (Cx<T> *)psi, a,
                        (const RotRec<T> *)rots, chunks, rin, nout);

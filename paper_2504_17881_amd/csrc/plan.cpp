@@ -463,7 +463,20 @@ struct Builder {
                 ++p;
                 continue;
             }
-            size_t got = r.kind == kTile ? emit_tile(p, r.g, q) : emit_span(p, q);
+            size_t got;
+            if (r.kind == kTile) {
+                // the fewest virtual qubits that still cover [p, q): longer
+                // contiguous tiles stream faster
+                int g = r.g;
+                for (int h = 0; h < r.g; ++h)
+                    if (cfg.B - h >= kMinTileLow && p + tile_len(p, h) >= q) {
+                        g = h;
+                        break;
+                    }
+                got = emit_tile(p, g, q);
+            } else {
+                got = emit_span(p, q);
+            }
             if (got <= p) {
                 emit_plain(p);
                 got = p + 1;
@@ -552,7 +565,7 @@ static void default_cfg(prx_dtype dt, PlanCfg &c) {
     c.m = 4;
     c.span_m = 4;
     c.max_fuse = 128;
-    c.max_virtual = kMaxVirtual;
+    c.max_virtual = 8;
     c.renorm_every = (dt == PRX_C64) ? 1 : -1;
     c.commuting = false;
 }
@@ -786,7 +799,7 @@ static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws
             std::memset(&a, 0, sizeof(a));
             for (int k = 0; k < ps.g; ++k) {
                 a.vmask[k] = ps.vmask[k];
-                a.tpivot[k] = (uint8_t)ps.tpivot[k];
+                a.tpivots |= (uint64_t)(ps.tpivot[k] & 63u) << (6 * k);
             }
             // slot u NT of the tile-set: tile (u NT) >> b, offset (u NT) mod 2^b
             const uint32_t nt = 1u << (ps.B - ps.m);

@@ -82,11 +82,11 @@ prx_status prx_autotune(void *psi, int n, prx_dtype dtype, const prx_sched *sche
     if (sched->n != n) return fail(PRX_ERR_INVALID, "n differs from the schedule's n");
     hipStream_t s = (hipStream_t)stream;
     struct Shape { int B, m; };
-    const Shape shapes[] = {{10, 3}, {10, 4}, {11, 4}, {12, 4}, {12, 5}, {13, 4}, {13, 5}};
+    const Shape shapes[] = {{10, 3}, {10, 4}, {11, 4}, {12, 4}, {12, 5}, {13, 4}, {13, 5}, {14, 4}};
     std::vector<prx_plan_opts> cands;
     for (const Shape &sh : shapes) {
         if (!tile_supported(dtype, sh.B, sh.m) || n < sh.B + 1) continue;
-        for (int g : {1, 2, 3, 5, 8}) {
+        for (int g : {1, 2, 3, 5, 8, 10}) {
             if (sh.B - g < kMinTileLow) continue;
             for (int f : {64, 128}) {
                 prx_plan_opts o;

@@ -74,13 +74,13 @@ class prx_pass_info(ctypes.Structure):
                 ("B", ctypes.c_int), ("b", ctypes.c_int), ("g", ctypes.c_int),
                 ("m", ctypes.c_int),
                 ("basis", ctypes.c_uint64 * 6), ("pivot", ctypes.c_uint32 * 6),
-                ("vmask", ctypes.c_uint64 * 8), ("tpivot", ctypes.c_uint32 * 8),
+                ("vmask", ctypes.c_uint64 * 10), ("tpivot", ctypes.c_uint32 * 10),
                 ("scale", ctypes.c_double), ("fscale", ctypes.c_double * 6),
                 ("norm_out", ctypes.c_int), ("renorm_in", ctypes.c_int)]
 
 
 class prx_chunk_info(ctypes.Structure):
-    _fields_ = [("basis", ctypes.c_uint32 * 6), ("cvec", ctypes.c_uint32 * 9),
+    _fields_ = [("basis", ctypes.c_uint32 * 6), ("cvec", ctypes.c_uint32 * 10),
                 ("fscale", ctypes.c_double * 6), ("rot_begin", _sz), ("rot_count", _sz)]
 
 

@@ -69,6 +69,7 @@ SHAPES = [
     dict(tile_qubits=12, chunk_rank=4, max_virtual=2),
     dict(tile_qubits=12, chunk_rank=5),
     dict(tile_qubits=13, chunk_rank=4, max_virtual=2, span_max=2),
+    dict(tile_qubits=14, chunk_rank=4, span_max=2),
     dict(tile_qubits=10, chunk_rank=4, max_virtual=5, span_max=2),
     dict(tile_qubits=11, chunk_rank=4, max_virtual=4, span_max=2),
     dict(span_max=1),
@@ -85,8 +86,8 @@ SHAPES = [
 def test_fused_shapes_jw_trotter(opts, dtype):
     """Every instantiated tile shape, span rank and planner option against
     the oracle on a SUFFIX-ordered JW Trotter run (tiles and spans mixed)."""
-    if dtype == P.PRX_C128 and opts.get("tile_qubits") == 13:
-        pytest.skip("c128 13-qubit tiles exceed the LDS budget")
+    if dtype == P.PRX_C128 and opts.get("tile_qubits", 0) >= 13:
+        pytest.skip("complex128 tiles above 12 qubits are not built (LDS budget)")
     n = 15
     x, z, h = synth.jw_hamiltonian(n, 400, 11)
     H = P.prx_ham_create(n, x, z, h)
@@ -104,21 +105,21 @@ def test_fused_shapes_jw_trotter(opts, dtype):
     P.prx_ham_destroy(H)
 
 
-@pytest.mark.parametrize("dtype", [P.PRX_C128, P.PRX_C64])
-@pytest.mark.parametrize("g", [6, 8])
-def test_many_virtual_qubits(g, dtype):
-    """Tile-sets of 2^g tiles with as few as 16 contiguous amplitudes: n = 20,
-    12-qubit tile frame, spans limited so that tiles take the high X parts."""
-    n = 20
-    x, z, h = synth.jw_hamiltonian(n, 300, 21)
+@pytest.mark.parametrize("n,B,g,dtype", [
+    (20, 12, 6, P.PRX_C64), (20, 12, 8, P.PRX_C64), (20, 11, 6, P.PRX_C128),
+    (20, 11, 8, P.PRX_C128), (22, 13, 8, P.PRX_C64), (24, 14, 10, P.PRX_C64)])
+def test_many_virtual_qubits(n, B, g, dtype):
+    """Tile-sets of 2^g tiles with as few as 16 contiguous amplitudes (the
+    13- and 14-qubit frames run persistent workgroups), spans limited so that
+    tiles take the high X parts."""
+    x, z, h = synth.jw_hamiltonian(n, 300 if n < 24 else 200, 21)
     H = P.prx_ham_create(n, x, z, h)
     s = P.prx_sched_trotter(H, 1, 2.0, 1, P.PRX_REORDER_SUFFIX)
     _, rx, rz, rp = P.prx_sched_view(s)
     psi0 = synth.gaussian_state(n, 22)
     ref = sv.c_apply_rotations(psi0, rx, rz, rp)
-    opts = dict(tile_qubits=12 if dtype == P.PRX_C64 else 11, chunk_rank=4, max_virtual=g,
-                span_max=2, max_fuse=128)
-    print(f"[many virtual g={g} dtype={dtype}]", flush=True)
+    opts = dict(tile_qubits=B, chunk_rank=4, max_virtual=g, span_max=2, max_fuse=128)
+    print(f"[many virtual n={n} B={B} g={g} dtype={dtype}]", flush=True)
     pl = P.prx_plan_create(s, n, dtype, 0, len(rx), P.PRX_FUSED, opts)
     gs = [P.prx_plan_pass(pl, i)["g"] for i in range(P.prx_plan_get_info(pl)["passes"])]
     assert max(gs) >= min(g, 5)
