@@ -165,7 +165,10 @@ def main() -> int:
         scratch = torch.zeros(1 << n, dtype=torch.complex64, device=dev)
         scratch[k0] = 1.0
         tws = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
-        tuned, trials = P.prx_autotune(scratch, n, P.PRX_C64, sub, tws)
+        def _trial(o, ms):
+            print(f"[bench] tune {({k: v for k, v in o.items() if v})} {ms:.1f} ms",
+                  file=sys.stderr, flush=True)
+        tuned, trials = P.prx_autotune(scratch, n, P.PRX_C64, sub, tws, progress=_trial)
         os.makedirs(os.path.dirname(os.path.abspath(args.autotune_save)), exist_ok=True)
         P.prx_autotune_save(args.autotune_save)
         print(f"[bench] autotune: {trials} trials, best {tuned}", file=sys.stderr, flush=True)

@@ -362,6 +362,13 @@ void prx_graph_destroy(prx_graph *g);
 prx_status prx_autotune(void *psi, int n, prx_dtype dtype, const prx_sched *sched, void *ws,
                         size_t ws_bytes, void *stream, prx_plan_opts *best_out,
                         int *trials_out);
+/* The same, calling progress(opts, ms, user) after each timed setting
+ * (progress may be null). */
+typedef void (*prx_tune_progress_fn)(const prx_plan_opts *opts, float ms, void *user);
+prx_status prx_autotune_progress(void *psi, int n, prx_dtype dtype, const prx_sched *sched,
+                                 void *ws, size_t ws_bytes, void *stream,
+                                 prx_plan_opts *best_out, int *trials_out,
+                                 prx_tune_progress_fn progress, void *user);
 /* Reads/writes the autotune cache as JSON text ({"gfx950/n/dtype": {...}}). */
 prx_status prx_autotune_save(const char *path);
 prx_status prx_autotune_load(const char *path);

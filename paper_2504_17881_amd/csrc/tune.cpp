@@ -77,6 +77,14 @@ extern "C" {
 prx_status prx_autotune(void *psi, int n, prx_dtype dtype, const prx_sched *sched, void *ws,
                         size_t ws_bytes, void *stream, prx_plan_opts *best_out,
                         int *trials_out) {
+    return prx_autotune_progress(psi, n, dtype, sched, ws, ws_bytes, stream, best_out, trials_out,
+                                 nullptr, nullptr);
+}
+
+prx_status prx_autotune_progress(void *psi, int n, prx_dtype dtype, const prx_sched *sched,
+                                 void *ws, size_t ws_bytes, void *stream,
+                                 prx_plan_opts *best_out, int *trials_out,
+                                 prx_tune_progress_fn progress, void *user) {
     if (!psi || !sched || !ws) return fail(PRX_ERR_INVALID, "null pointer");
     if (dtype != PRX_C64 && dtype != PRX_C128) return fail(PRX_ERR_INVALID, "bad dtype");
     if (sched->n != n) return fail(PRX_ERR_INVALID, "n differs from the schedule's n");
@@ -120,6 +128,7 @@ prx_status prx_autotune(void *psi, int n, prx_dtype dtype, const prx_sched *sche
         if (P->ws.total <= ws_bytes) {
             st = time_plan(P, psi, ws, ws_bytes, s, &ms);
             if (st == PRX_OK) {
+                if (progress) progress(&o, ms, user);
                 ++trials;
                 if (trials == 1 || ms < best_ms) {
                     best_ms = ms;

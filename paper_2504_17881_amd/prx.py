@@ -148,6 +148,9 @@ _sig("prx_graph_launch", _st, _vp, _vp)
 _sig("prx_graph_destroy", None, _vp)
 _sig("prx_autotune", _st, _vp, _i, _i, _vp, _vp, _sz, _vp, ctypes.POINTER(prx_plan_opts),
      ctypes.POINTER(_i))
+_TUNE_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.POINTER(prx_plan_opts), ctypes.c_float, _vp)
+_sig("prx_autotune_progress", _st, _vp, _i, _i, _vp, _vp, _sz, _vp, ctypes.POINTER(prx_plan_opts),
+     ctypes.POINTER(ctypes.c_int), _TUNE_PROGRESS, _vp)
 _sig("prx_autotune_save", _st, ctypes.c_char_p)
 _sig("prx_autotune_load", _st, ctypes.c_char_p)
 _sig("prx_autotune_lookup", _st, _i, _i, ctypes.POINTER(prx_plan_opts))
@@ -480,12 +483,27 @@ def prx_graph_destroy(graph: int) -> None:
 
 # ---------------------------------------------------------------- autotune
 
-def prx_autotune(psi, n: int, dtype: int, sched: int, ws, stream=None, ws_bytes=None):
+def prx_autotune(psi, n: int, dtype: int, sched: int, ws, stream=None, ws_bytes=None,
+                 progress=None):
+    """progress(opts: dict, ms: float) is called after each timed setting."""
     best = prx_plan_opts()
     trials = ctypes.c_int()
-    _check(_lib.prx_autotune(_ptr(psi), n, dtype, sched, _ptr(ws), _nbytes(ws, ws_bytes),
-                             _stream(stream), ctypes.byref(best), ctypes.byref(trials)))
+    if progress is None:
+        _check(_lib.prx_autotune(_ptr(psi), n, dtype, sched, _ptr(ws), _nbytes(ws, ws_bytes),
+                                 _stream(stream), ctypes.byref(best), ctypes.byref(trials)))
+    else:
+        def _cb(o, ms, _user):
+            progress({f: getattr(o.contents, f) for f, _ in prx_plan_opts._fields_}, float(ms))
+        cb = _TUNE_PROGRESS(_cb)
+        _check(_lib.prx_autotune_progress(_ptr(psi), n, dtype, sched, _ptr(ws),
+                                          _nbytes(ws, ws_bytes), _stream(stream),
+                                          ctypes.byref(best), ctypes.byref(trials), cb, None))
     return {f: getattr(best, f) for f, _ in prx_plan_opts._fields_}, trials.value
+
+
+def prx_autotune_progress(psi, n: int, dtype: int, sched: int, ws, progress, stream=None,
+                          ws_bytes=None):
+    return prx_autotune(psi, n, dtype, sched, ws, stream, ws_bytes, progress=progress)
 
 
 def prx_autotune_save(path: str) -> None:
