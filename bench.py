@@ -117,7 +117,8 @@ def main() -> int:
     ap.add_argument("--autotune-save", default=None,
                     help="run the autotuner on the first --tune-rotations rotations first and "
                          "save its cache to this path")
-    ap.add_argument("--tune-rotations", type=int, default=1000)
+    ap.add_argument("--tune-rotations", type=int, default=5000,
+                    help="rotations of the schedule timed per autotune setting (default: one Trotter step)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="GIB",
                     help="first run torch copies of GIB GiB (3 launches): the known-size "
                          "reference that scales hardware byte counters")
