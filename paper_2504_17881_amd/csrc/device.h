@@ -47,6 +47,17 @@ __device__ __forceinline__ float flip(float v, uint32_t p) {
 __device__ __forceinline__ double flip(double v, uint32_t p) {
     return __longlong_as_double(__double_as_longlong(v) ^ ((uint64_t)p << 63));
 }
+// The same for any count p: adding (p << 31) to the bit pattern flips the
+// sign bit exactly when p is odd (the carry out of bit 31 is dropped), which
+// is one shift-add instruction.
+__device__ __forceinline__ float flip_add(float v, uint32_t p) {
+    return __uint_as_float(__float_as_uint(v) + (p << 31));
+}
+__device__ __forceinline__ double flip_add(double v, uint32_t p) {
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t hi = (uint32_t)(u >> 32) + (p << 31);
+    return __longlong_as_double((u & 0xffffffffull) | ((uint64_t)hi << 32));
+}
 
 // ------------------------------------------------------ register updates
 //
@@ -272,16 +283,30 @@ __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t
         const uint32_t zeta = (rec.info >> 8) & 0xffu;
         // uniform part of the sign, then one AND and one count per lane
         const uint32_t tpar = (uint32_t)__builtin_popcountll(tbase & rec.zhigh);
-        uint32_t s0;
-        if constexpr (sizeof(K0) == 4)
-            s0 = ((uint32_t)__builtin_popcount(k0 & (uint32_t)rec.z) + tpar) & 1u;
-        else
-            s0 = ((uint32_t)__builtin_popcountll(k0 & rec.z) + tpar) & 1u;
+        uint32_t cnt;  // parity in bit 0
+        if constexpr (sizeof(K0) == 4) {
+            // one AND and one count that adds the uniform part
+            const uint32_t m = k0 & (uint32_t)rec.z;
+            asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(cnt) : "v"(m), "s"(tpar));
+        } else {
+            cnt = (uint32_t)__builtin_popcountll(k0 & rec.z) + tpar;
+        }
+        const uint32_t s0 = cnt & 1u;
         if constexpr (M <= kStaticSignRank) {
             // tau_a arrives multiplied by (-1)^zeta_slot: both pair
             // coefficients then share the pattern (-1)^parity(c(v) & zp)
-            const T ga = pin(flip(rec.tau_a, s0));
-            const T gb = pin(flip(rec.tau_b, s0));
+            T ga, gb;
+            if constexpr (sizeof(T) == 4) {
+                // one shift-add per coefficient (see flip_add)
+                uint32_t ua, ub;
+                asm("v_lshl_add_u32 %0, %1, 31, %2" : "=v"(ua) : "v"(cnt), "s"(__float_as_uint(rec.tau_a)));
+                asm("v_lshl_add_u32 %0, %1, 31, %2" : "=v"(ub) : "v"(cnt), "s"(__float_as_uint(rec.tau_b)));
+                ga = __uint_as_float(ua);
+                gb = __uint_as_float(ub);
+            } else {
+                ga = pin(flip_add(rec.tau_a, cnt));
+                gb = pin(flip_add(rec.tau_b, cnt));
+            }
             rot_var<T, M, 0, (M << M) + 1>(amp, ga, gb, (rec.info >> 16) & 0xffu, zeta);
             continue;
         }
