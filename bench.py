@@ -101,6 +101,58 @@ def cpu_baseline(x, z, phi, n: int, k0: int, budget_s: float, max_rot: int):
     }
 
 
+def fusion_sweep(ns, reps: int) -> int:
+    """Fusion-depth curve: groups of L = 1, 10, 100 rotations that share one
+    high X part (random low X and Z parts, angles U[-pi, pi]), applied as one
+    sweep per rotation (plain) and as fused passes, at several n and both
+    precisions.  One JSON line per (dtype, n, L, kernel) with the time per
+    rotation and the HBM traffic of the passes against the 8 TB/s peak."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2504_17881_amd import prx as P
+    dev = torch.device("cuda:0")
+    low = 8  # the shared high X part starts above every tile's low qubits
+    for dt, name, s in ((P.PRX_C64, "c64", 8), (P.PRX_C128, "c128", 16)):
+        for n in ns:
+            psi = torch.zeros(1 << n, dtype=torch.complex64 if s == 8 else torch.complex128,
+                              device=dev)
+            psi[0] = 1.0
+            for L in (1, 10, 100):
+                rng = np.random.default_rng(1000 * n + L)
+                xh = int(rng.integers(1, 1 << (n - low)))
+                x = ((np.uint64(xh) << np.uint64(low)) |
+                     rng.integers(0, 1 << low, size=L).astype(np.uint64)).astype(np.uint64)
+                z = rng.integers(0, 1 << n, size=L, dtype=np.uint64)
+                phi = rng.uniform(-np.pi, np.pi, size=L)
+                sched = P.prx_sched_from_rotations(n, x, z, phi)
+                for kern, kname in ((P.PRX_PLAIN, "plain"), (P.PRX_FUSED, "fused")):
+                    pl = P.prx_plan_create(sched, n, dt, 0, L, kern)
+                    info = P.prx_plan_get_info(pl)
+                    ws = torch.empty(max(info["workspace_bytes"], 256), dtype=torch.uint8,
+                                     device=dev)
+                    P.prx_plan_upload(pl, ws)
+                    P.prx_plan_execute_timed(pl, psi, ws)  # warm-up
+                    tot = 0.0
+                    for _ in range(reps):
+                        pm, rm = P.prx_plan_execute_timed(pl, psi, ws)
+                        tot += float(pm.sum()) + float(rm.sum())
+                    ms = tot / reps
+                    nbytes = info["passes"] * 2.0 * (1 << n) * s
+                    print(json.dumps({"dtype": name, "n": n, "L": L, "kernel": kname,
+                                      "passes": info["passes"], "ms": ms,
+                                      "ms_per_rotation": ms / L,
+                                      "updates_per_s": L * float(1 << n) / (ms * 1e-3),
+                                      "hbm_frac": nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}),
+                          flush=True)
+                    P.prx_plan_destroy(pl)
+                    del ws
+                P.prx_sched_destroy(sched)
+            del psi
+            torch.cuda.empty_cache()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,11 +174,17 @@ def main() -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="GIB",
                     help="first run torch copies of GIB GiB (3 launches): the known-size "
                          "reference that scales hardware byte counters")
+    ap.add_argument("--fusion-sweep", action="store_true",
+                    help="instead of the benchmark, print the fusion-depth curve (plain against "
+                         "fused for groups of 1, 10, 100 rotations sharing a high X part)")
+    ap.add_argument("--sweep-n", default="16,20,24,28,32")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path is a "
               "single-device kernel and this build has no multi-GPU path.", file=sys.stderr)
         return 2
+    if args.fusion_sweep:
+        return fusion_sweep([int(v) for v in args.sweep_n.split(",")], max(1, args.steps))
 
     import numpy as np
     import torch
