@@ -48,9 +48,14 @@ def test_autotune_picks_a_setting_and_auto_plan_is_exact():
     _, rx, rz, rp = P.prx_sched_view(s)
     scratch = basis_state(n, 3, P.PRX_C128)
     ws = workspace(64 << 20)
-    best, trials = P.prx_autotune(scratch, n, P.PRX_C128, s, ws)
+    seen = []
+    best, trials = P.prx_autotune(scratch, n, P.PRX_C128, s, ws,
+                                  progress=lambda o, ms: seen.append((o, ms)))
     print(f"[autotune] {trials} trials, best {best}", flush=True)
     assert trials >= 3 and P.prx_autotune_lookup(n, P.PRX_C128) == best
+    # every timed setting is reported once, and the best is the fastest of them
+    assert len(seen) == trials and all(ms > 0 for _, ms in seen)
+    assert min(seen, key=lambda t: t[1])[0] == best
     k0 = synth.basis_index(n)
     psi0 = np.zeros(1 << n, dtype=np.complex128)
     psi0[k0] = 1
