@@ -153,6 +153,9 @@ typedef struct {
                             keeps at least 16 contiguous amplitudes (default 8) */
     int renorm_every;    /* C64: renormalise in FP64 every k passes (default 1; -1 = never) */
     int commuting;       /* 1: planner may swap adjacent commuting rotations (default 0) */
+    int tile_only;       /* 1: every pass a tile pass, as batched samples of >= tile_qubits
+                            qubits are planned (default 0); INVALID with PRX_PLAIN or
+                            n < tile_qubits */
 } prx_plan_opts;
 
 /* Summary of a plan. */
@@ -300,20 +303,23 @@ prx_status prx_renormalize(void *psi, int n, prx_dtype dtype, void *ws, size_t w
                            void *stream);
 
 /* ------------------------------------------------------------------ */
-/* Batched samples in one persistent launch.                           */
+/* Batched samples: shared round launches.                            */
 /* ------------------------------------------------------------------ */
 
 typedef struct prx_batch prx_batch;
 typedef struct prx_graph prx_graph;
 
 /* Plans S independent runs: sample s applies sched[s] to its own state
- * (2^n[s] amplitudes of dtype) and reports <basis_idx[s]|psi_s>.  Each
- * sample's schedule is segmented into span passes of a fixed rank; round p
- * applies pass p of every sample that has one, as one grid-stride kernel over
- * that round's (sample, slice) items, so all samples share every launch and
- * no workgroup waits on another.  Host only; no device calls.  INVALID if
- * S = 0, an n[s] is outside [6, 34], sched[s]->n != n[s], or basis_idx[s] >=
- * 2^n[s]. */
+ * (2^n[s] amplitudes of dtype) and reports <basis_idx[s]|psi_s> (the
+ * observable of the qDRIFT and partially randomised estimators, Methods).
+ * A sample of at least 12 qubits (complex64; 11 for complex128) is
+ * segmented into tile passes of that many tile qubits with up to 8 virtual
+ * qubits; a smaller one into span passes of rank 4.  Round p applies pass p
+ * of every sample that has one, as one grid-stride kernel over that round's
+ * (sample, tile-set) items and one over its (sample, slice) items, so all
+ * samples share every launch and no workgroup waits on another.  Host only;
+ * no device calls.  INVALID if S = 0, an n[s] is outside [6, 34],
+ * sched[s]->n != n[s], or basis_idx[s] >= 2^n[s]. */
 prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sched,
                             prx_dtype dtype, const uint64_t *basis_idx, prx_batch **out);
 size_t prx_batch_workspace_bytes(const prx_batch *b);
@@ -322,8 +328,8 @@ size_t prx_batch_workspace_bytes(const prx_batch *b);
  * `ws`; waits for the copies. */
 prx_status prx_batch_upload(prx_batch *b, void *const *psi, void *ws, size_t ws_bytes,
                             void *stream);
-/* Enqueues, on `stream`, kernels only: one per round (the largest pass
- * count among the samples) and the overlap read-out into overlaps_dev
+/* Enqueues, on `stream`, kernels only: at most two per round (the rounds
+ * being the largest pass count among the samples) and the overlap read-out into overlaps_dev
  * (device array of 2*S doubles, (re, im) per sample).  It can therefore be
  * replayed and captured in one graph (prx_batch_graph). */
 prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,

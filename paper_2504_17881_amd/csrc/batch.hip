@@ -1,13 +1,17 @@
 // Batched execution of many independent samples (qDRIFT or partially
 // randomised draws, circuits of uneven qubit counts).
 //
-// Each sample's schedule is planned into span passes of fixed rank M (the
-// basis padded with unused high directions), so every pass of a sample has
-// the same 2^(n-M) cosets, split into Q slices of at most kSliceCosets.
-// Round p applies pass p of every sample that has one: a single grid-stride
-// kernel over that round's (sample, slice) items.  Kernel boundaries order
-// the rounds, so no workgroup ever waits on another; the whole sequence of
-// round kernels is enqueued back to back (and can be captured as one graph).
+// Samples that hold a tile frame (n >= B: 12 qubits at complex64, 11 at
+// complex128) are planned into tile passes only, with up to 8 virtual
+// qubits: a random-order qDRIFT sequence then fuses 2-2.5 times more
+// rotations per HBM pass than with spans.  Smaller samples are planned into
+// span passes of fixed rank M (the basis padded with unused high
+// directions), every pass with the same 2^(n-M) cosets split into Q slices
+// of at most kSliceCosets.  Round p applies pass p of every sample that has
+// one: one grid-stride kernel over that round's (sample, tile-set) items and
+// one over its (sample, slice) items.  Kernel boundaries order the rounds,
+// so no workgroup ever waits on another; the whole sequence of round kernels
+// is enqueued back to back (and can be captured as one graph).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -21,6 +25,9 @@ namespace prx {
 
 static constexpr int kBatchRank = 4;
 static constexpr uint64_t kSliceCosets = 8192;
+static constexpr int kBatchTileM = 4;
+static constexpr int kBatchMaxVirtual = 8;
+static int batch_tile_qubits(prx_dtype dt) { return dt == PRX_C64 ? 12 : 11; }
 
 struct BSample {
     uint64_t psi;       // device address of the state
@@ -96,6 +103,80 @@ __global__ void __launch_bounds__(256) k_batch_round(BatchArgs a, uint32_t p, ui
     }
 }
 
+// Tile-mode samples: tile passes of fixed (B, M).
+struct BTSample {
+    uint64_t psi;
+    uint32_t nsets;  // 2^(n - B) tile-sets per pass
+    uint32_t pass_begin, pass_count;
+    uint32_t n;
+};
+
+struct BatchTileArgs {
+    const BTSample *samples;
+    const TileArgs *passes;
+    const ChunkRec *chunks;
+    const void *rots;
+    const uint64_t *prefixW;  // S_t + 1 tile-set counts over the sorted samples
+    const uint32_t *order;
+};
+
+template <typename T, int B, int M>
+__global__ void __launch_bounds__(1 << (B - M))
+    k_batch_tile_round(BatchTileArgs a, uint32_t p, uint32_t active, uint64_t items) {
+    constexpr int NT = 1 << (B - M);
+    constexpr int PER = 1 << M;
+    __shared__ __align__(16) Cx<T> lds[1 << B];
+    unsigned char *lds_raw = reinterpret_cast<unsigned char *>(lds);
+    const uint32_t tid = threadIdx.x;
+    uint32_t tmask[B - M];
+    tile_thread_masks<B - M>(tid, tmask);
+    for (uint64_t j = blockIdx.x; j < items; j += gridDim.x) {
+        // last k < active with prefixW[k] <= j (uniform across the block)
+        uint32_t lo = 0, hi = active;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.prefixW[mid] <= j) lo = mid; else hi = mid;
+        }
+        const BTSample smp = a.samples[a.order[lo]];
+        const uint32_t w = (uint32_t)(j - a.prefixW[lo]);
+        const TileArgs *ta = a.passes + smp.pass_begin + p;
+        Cx<T> *psi = reinterpret_cast<Cx<T> *>(smp.psi);
+        // the set's base tile and this thread's slots (see k_tile)
+        const int b = ta->b, g = ta->g;
+        uint64_t tb = w;
+        for (int i = 0; i < g; ++i) tb = insert_zero64(tb, (uint32_t)(ta->tpivots >> (6 * i)) & 63u);
+        uint64_t c = tb;
+        const uint32_t v = tid >> b;
+        for (int i = 0; i < g; ++i)
+            if (v >> i & 1) c ^= ta->vmask[i];
+        const uint64_t base = (c << b) | (tid & ((1u << b) - 1u));
+        {
+            Cx<T> r[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) r[u] = psi[base ^ ta->uoff[u]];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
+        }
+        __syncthreads();
+        tile_chunks<T, B, M>(lds_raw, tmask, tb, a.chunks + ta->chunk_begin, ta->chunk_count,
+                             reinterpret_cast<const RotRec<T> *>(a.rots));
+        const T s = (T)ta->scale;
+        {
+            Cx<T> q[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) q[u] = lds[tid + (uint32_t)u * NT];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                Cx<T> o = q[u];
+                o.re *= s;
+                o.im *= s;
+                psi[base ^ ta->uoff[u]] = o;
+            }
+        }
+        __syncthreads();  // the next item overwrites the LDS
+    }
+}
+
 template <typename T>
 __global__ void k_batch_overlaps(const BSample *samples, uint32_t S, double *out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,11 +199,20 @@ struct prx_batch {
     std::vector<unsigned char> rots;
     std::vector<uint64_t> prefixQ;
     std::vector<uint32_t> order;
-    std::vector<uint32_t> round_active;  // samples with a pass in round p
-    uint64_t total_items = 0;
+    std::vector<uint32_t> round_active;  // span samples with a pass in round p
+    // tile-mode samples
+    std::vector<prx::BTSample> tsamples;
+    std::vector<uint32_t> tsrc;  // tile-mode sample -> sample
+    std::vector<prx::TileArgs> tpasses;
+    std::vector<prx::ChunkRec> tchunks;
+    std::vector<uint64_t> tprefix;
+    std::vector<uint32_t> torder;
+    std::vector<uint32_t> tround_active;
+    uint64_t total_items = 0, total_tile_items = 0;
     uint32_t rounds = 0;
     // workspace layout
     size_t off_samples = 0, off_passes = 0, off_rots = 0, off_prefix = 0, off_order = 0,
+           off_tsamples = 0, off_tpasses = 0, off_tchunks = 0, off_tprefix = 0, off_torder = 0,
            total = 0;
 };
 
@@ -154,19 +244,30 @@ prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sche
         b->S = S;
         b->dtype = dtype;
         const size_t rsz = dtype == PRX_C64 ? sizeof(RotRec<float>) : sizeof(RotRec<double>);
-        PlanCfg cfg;
-        cfg.span_only = true;
-        cfg.pad_rank = kBatchRank;
-        cfg.span_m = kBatchRank;
-        cfg.renorm_every = -1;
-        cfg.max_fuse = 64;
+        const int TB = batch_tile_qubits(dtype);
+        PlanCfg span_cfg;
+        span_cfg.span_only = true;
+        span_cfg.pad_rank = kBatchRank;
+        span_cfg.span_m = kBatchRank;
+        span_cfg.renorm_every = -1;
+        span_cfg.max_fuse = 64;
+        PlanCfg tile_cfg;
+        tile_cfg.tile_only = true;
+        tile_cfg.B = TB;
+        tile_cfg.m = kBatchTileM;
+        tile_cfg.renorm_every = -1;
+        tile_cfg.max_fuse = 128;
+        tile_cfg.max_virtual = kBatchMaxVirtual;
         for (size_t s = 0; s < S; ++s) {
+            const bool tile = n[s] >= TB;
             prx_plan *P = nullptr;
-            prx_status st = plan_create_cfg(sched[s], n[s], dtype, cfg, &P);
+            prx_status st = plan_create_cfg(sched[s], n[s], dtype, tile ? tile_cfg : span_cfg, &P);
             if (st != PRX_OK) {
                 delete b;
                 return st;
             }
+            // every sample keeps a BSample (state address and overlap index);
+            // a tile-mode sample has no span passes
             BSample sm;
             std::memset(&sm, 0, sizeof(sm));
             sm.n = (uint32_t)n[s];
@@ -174,27 +275,55 @@ prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sche
             sm.Q = (uint32_t)((sm.ncos + kSliceCosets - 1) / kSliceCosets);
             sm.basis_idx = basis_idx[s];
             sm.pass_begin = (uint32_t)b->passes.size();
-            sm.pass_count = (uint32_t)P->passes.size();
             const uint32_t rot_base = (uint32_t)(b->rots.size() / rsz);
-            for (const Pass &ps : P->passes) {
-                BPass bp;
-                std::memset(&bp, 0, sizeof(bp));
-                for (int i = 0; i < kBatchRank; ++i) {
-                    bp.basis[i] = ps.basis[i];
-                    bp.pivot[i] = ps.pivot[i];
+            if (tile) {
+                BTSample ts;
+                std::memset(&ts, 0, sizeof(ts));
+                ts.n = (uint32_t)n[s];
+                ts.nsets = (uint32_t)(1ull << (n[s] - TB));
+                ts.pass_begin = (uint32_t)b->tpasses.size();
+                ts.pass_count = (uint32_t)P->passes.size();
+                const uint32_t chunk_base = (uint32_t)b->tchunks.size();
+                for (const Pass &ps : P->passes) {
+                    if (ps.kind != kTile || ps.B != TB || ps.m != kBatchTileM) {
+                        prx_plan_destroy(P);
+                        delete b;
+                        return fail(PRX_ERR_UNSUPPORTED, "tile-only plan with another pass kind");
+                    }
+                    TileArgs ta;
+                    tile_args(n[s], ps, ta);
+                    ta.chunk_begin += chunk_base;
+                    b->tpasses.push_back(ta);
                 }
-                bp.rot_begin = rot_base + (uint32_t)ps.r0;
-                bp.rot_count = (uint32_t)(ps.r1 - ps.r0);
-                bp.scale = ps.scale;
-                for (int i = 0; i < kBatchRank; ++i) bp.fscale[i] = ps.fscale[i];
-                b->passes.push_back(bp);
+                for (ChunkRec ch : P->chunks) {
+                    ch.rot_begin += rot_base;
+                    b->tchunks.push_back(ch);
+                }
+                b->tsamples.push_back(ts);
+            } else {
+                sm.pass_count = (uint32_t)P->passes.size();
+                for (const Pass &ps : P->passes) {
+                    BPass bp;
+                    std::memset(&bp, 0, sizeof(bp));
+                    for (int i = 0; i < kBatchRank; ++i) {
+                        bp.basis[i] = ps.basis[i];
+                        bp.pivot[i] = ps.pivot[i];
+                    }
+                    bp.rot_begin = rot_base + (uint32_t)ps.r0;
+                    bp.rot_count = (uint32_t)(ps.r1 - ps.r0);
+                    bp.scale = ps.scale;
+                    for (int i = 0; i < kBatchRank; ++i) bp.fscale[i] = ps.fscale[i];
+                    b->passes.push_back(bp);
+                }
             }
             b->rots.insert(b->rots.end(), P->rot_table.begin(), P->rot_table.end());
             b->samples.push_back(sm);
+            if (tile) b->tsrc.push_back((uint32_t)s);
             prx_plan_destroy(P);
         }
         // samples sorted by pass count (descending): round p's active samples
-        // are a prefix of this order
+        // are a prefix of this order (tile-mode samples sort last with no
+        // span passes)
         b->order.resize(S);
         for (size_t s = 0; s < S; ++s) b->order[s] = (uint32_t)s;
         std::stable_sort(b->order.begin(), b->order.end(), [&](uint32_t x, uint32_t y) {
@@ -203,20 +332,40 @@ prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sche
         b->prefixQ.assign(S + 1, 0);
         for (size_t k = 0; k < S; ++k)
             b->prefixQ[k + 1] = b->prefixQ[k] + b->samples[b->order[k]].Q;
-        b->rounds = b->samples[b->order[0]].pass_count;
+        const size_t St = b->tsamples.size();
+        b->torder.resize(St);
+        for (size_t s = 0; s < St; ++s) b->torder[s] = (uint32_t)s;
+        std::stable_sort(b->torder.begin(), b->torder.end(), [&](uint32_t x, uint32_t y) {
+            return b->tsamples[x].pass_count > b->tsamples[y].pass_count;
+        });
+        b->tprefix.assign(St + 1, 0);
+        for (size_t k = 0; k < St; ++k)
+            b->tprefix[k + 1] = b->tprefix[k] + b->tsamples[b->torder[k]].nsets;
+        const uint32_t span_rounds = b->samples[b->order[0]].pass_count;
+        const uint32_t tile_rounds = St ? b->tsamples[b->torder[0]].pass_count : 0;
+        b->rounds = std::max(span_rounds, tile_rounds);
         b->round_active.assign(b->rounds, 0);
-        size_t active = S;
+        b->tround_active.assign(b->rounds, 0);
+        size_t active = S, tactive = St;
         for (uint32_t p = 0; p < b->rounds; ++p) {
             while (active > 0 && b->samples[b->order[active - 1]].pass_count <= p) --active;
+            while (tactive > 0 && b->tsamples[b->torder[tactive - 1]].pass_count <= p) --tactive;
             b->round_active[p] = (uint32_t)active;
+            b->tround_active[p] = (uint32_t)tactive;
             b->total_items += b->prefixQ[active];
+            b->total_tile_items += b->tprefix[tactive];
         }
         size_t o = 0;
-        b->off_samples = o; o = al256(o + S * sizeof(BSample));
-        b->off_passes = o;  o = al256(o + b->passes.size() * sizeof(BPass));
-        b->off_rots = o;    o = al256(o + b->rots.size());
-        b->off_prefix = o;  o = al256(o + b->prefixQ.size() * sizeof(uint64_t));
-        b->off_order = o;   o = al256(o + S * sizeof(uint32_t));
+        b->off_samples = o;  o = al256(o + S * sizeof(BSample));
+        b->off_passes = o;   o = al256(o + b->passes.size() * sizeof(BPass));
+        b->off_rots = o;     o = al256(o + b->rots.size());
+        b->off_prefix = o;   o = al256(o + b->prefixQ.size() * sizeof(uint64_t));
+        b->off_order = o;    o = al256(o + S * sizeof(uint32_t));
+        b->off_tsamples = o; o = al256(o + St * sizeof(BTSample));
+        b->off_tpasses = o;  o = al256(o + b->tpasses.size() * sizeof(TileArgs));
+        b->off_tchunks = o;  o = al256(o + b->tchunks.size() * sizeof(ChunkRec));
+        b->off_tprefix = o;  o = al256(o + b->tprefix.size() * sizeof(uint64_t));
+        b->off_torder = o;   o = al256(o + St * sizeof(uint32_t));
         b->total = o;
     } catch (const std::bad_alloc &) {
         delete b;
@@ -238,6 +387,7 @@ prx_status prx_batch_upload(prx_batch *b, void *const *psi, void *ws, size_t ws_
             return fail(PRX_ERR_INVALID, "null or misaligned state pointer");
         b->samples[s].psi = (uint64_t)(uintptr_t)psi[s];
     }
+    for (size_t t = 0; t < b->tsamples.size(); ++t) b->tsamples[t].psi = b->samples[b->tsrc[t]].psi;
     hipStream_t st = (hipStream_t)stream;
     char *w = (char *)ws;
     PRX_HIP(hipMemcpyAsync(w + b->off_samples, b->samples.data(), b->S * sizeof(BSample),
@@ -251,6 +401,21 @@ prx_status prx_batch_upload(prx_batch *b, void *const *psi, void *ws, size_t ws_
                            b->prefixQ.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     PRX_HIP(hipMemcpyAsync(w + b->off_order, b->order.data(), b->S * sizeof(uint32_t),
                            hipMemcpyHostToDevice, st));
+    const size_t St = b->tsamples.size();
+    if (St) {
+        PRX_HIP(hipMemcpyAsync(w + b->off_tsamples, b->tsamples.data(), St * sizeof(BTSample),
+                               hipMemcpyHostToDevice, st));
+        PRX_HIP(hipMemcpyAsync(w + b->off_tpasses, b->tpasses.data(),
+                               b->tpasses.size() * sizeof(TileArgs), hipMemcpyHostToDevice, st));
+        if (!b->tchunks.empty())
+            PRX_HIP(hipMemcpyAsync(w + b->off_tchunks, b->tchunks.data(),
+                                   b->tchunks.size() * sizeof(ChunkRec), hipMemcpyHostToDevice,
+                                   st));
+        PRX_HIP(hipMemcpyAsync(w + b->off_tprefix, b->tprefix.data(),
+                               b->tprefix.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+        PRX_HIP(hipMemcpyAsync(w + b->off_torder, b->torder.data(), St * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, st));
+    }
     PRX_HIP(hipStreamSynchronize(st));
     return PRX_OK;
 }
@@ -267,21 +432,43 @@ prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
     a.rots = w + b->off_rots;
     a.prefixQ = (const uint64_t *)(w + b->off_prefix);
     a.order = (const uint32_t *)(w + b->off_order);
+    BatchTileArgs ta;
+    ta.samples = (const BTSample *)(w + b->off_tsamples);
+    ta.passes = (const TileArgs *)(w + b->off_tpasses);
+    ta.chunks = (const ChunkRec *)(w + b->off_tchunks);
+    ta.rots = w + b->off_rots;
+    ta.prefixW = (const uint64_t *)(w + b->off_tprefix);
+    ta.order = (const uint32_t *)(w + b->off_torder);
     int dev = 0, cus = 256;
     PRX_HIP(hipGetDevice(&dev));
     PRX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const uint64_t cap = (uint64_t)std::max(1, cus) * 8u;
+    const unsigned tile_threads = 1u << (batch_tile_qubits(b->dtype) - kBatchTileM);
     for (uint32_t p = 0; p < b->rounds; ++p) {
+        const uint32_t tactive = b->tround_active[p];
+        const uint64_t titems = b->tprefix[tactive];
+        if (titems) {
+            const unsigned grid = (unsigned)std::min<uint64_t>(titems, cap);
+            if (b->dtype == PRX_C64)
+                hipLaunchKernelGGL((k_batch_tile_round<float, 12, kBatchTileM>), dim3(grid),
+                                   dim3(tile_threads), 0, st, ta, p, tactive, titems);
+            else
+                hipLaunchKernelGGL((k_batch_tile_round<double, 11, kBatchTileM>), dim3(grid),
+                                   dim3(tile_threads), 0, st, ta, p, tactive, titems);
+            PRX_HIP(hipGetLastError());
+        }
         const uint32_t active = b->round_active[p];
         const uint64_t items = b->prefixQ[active];
-        const unsigned grid = (unsigned)std::min<uint64_t>(items, cap);
-        if (b->dtype == PRX_C64)
-            hipLaunchKernelGGL(k_batch_round<float>, dim3(grid), dim3(256), 0, st, a, p, active,
-                               items);
-        else
-            hipLaunchKernelGGL(k_batch_round<double>, dim3(grid), dim3(256), 0, st, a, p, active,
-                               items);
-        PRX_HIP(hipGetLastError());
+        if (items) {
+            const unsigned grid = (unsigned)std::min<uint64_t>(items, cap);
+            if (b->dtype == PRX_C64)
+                hipLaunchKernelGGL(k_batch_round<float>, dim3(grid), dim3(256), 0, st, a, p,
+                                   active, items);
+            else
+                hipLaunchKernelGGL(k_batch_round<double>, dim3(grid), dim3(256), 0, st, a, p,
+                                   active, items);
+            PRX_HIP(hipGetLastError());
+        }
     }
     const unsigned rb = (unsigned)((b->S + 255) / 256);
     if (b->dtype == PRX_C64)

@@ -323,6 +323,60 @@ __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t
     }
 }
 
+// ------------------------------------------------------------ tile chunks
+//
+// A tile-set of 2^B amplitudes sits in LDS (byte offsets from lds_raw).  For
+// each chunk, thread tid gathers the coset k0(tid) XOR span(basis) into
+// registers (k0(tid) = XOR of the chunk's complement vectors over the bits
+// of tid), applies the chunk's rotations, multiplies by the pending factors
+// of the coset labels and scatters back; a barrier separates chunks.
+
+// All-ones masks of the thread index bits: a chunk's representative is then
+// one AND-XOR per bit (pinned in registers).
+template <int NB>
+__device__ __forceinline__ void tile_thread_masks(uint32_t tid, uint32_t (&tmask)[NB]) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) tmask[i] = pin(0u - ((tid >> i) & 1u));
+}
+
+template <typename T, int B, int M>
+__device__ __forceinline__ void tile_chunks(unsigned char *lds_raw, const uint32_t (&tmask)[B - M],
+                                            uint64_t tb, const ChunkRec *__restrict__ chunks,
+                                            uint32_t count, const RotRec<T> *__restrict__ rots) {
+    // LDS byte offsets: the XOR of indices commutes with the element shift
+    constexpr uint32_t SH = sizeof(Cx<T>) == 8 ? 3u : 4u;
+    for (uint32_t c = 0; c < count; ++c) {
+        const ChunkRec ch = chunks[c];
+        uint32_t k0 = 0;
+#pragma unroll
+        for (int i = 0; i < B - M; ++i) k0 ^= tmask[i] & ch.cvec[i];
+        const uint32_t k0b = k0 << SH;
+        uint32_t Xb[1 << M];
+        Xb[0] = 0;
+#pragma unroll
+        for (int v = 1; v < (1 << M); ++v)
+            Xb[v] = Xb[v & (v - 1)] ^ (ch.basis[__builtin_ctz(v)] << SH);
+        Cx<T> amp[1 << M];
+#pragma unroll
+        for (int v = 0; v < (1 << M); ++v)
+            amp[v] = *reinterpret_cast<const Cx<T> *>(lds_raw + (k0b ^ Xb[v]));
+        apply_rots<T, M>(amp, k0, tb, rots + ch.rot_begin, ch.rot_count);
+#pragma unroll
+        for (int v = 0; v < (1 << M); ++v) {
+            T f;
+            if constexpr (sizeof(T) == 4)
+                f = ch.facf[v];
+            else
+                f = ch.facd[v];
+            Cx<T> o;
+            o.re = amp[v].re * f;
+            o.im = amp[v].im * f;
+            *reinterpret_cast<Cx<T> *>(lds_raw + (k0b ^ Xb[v])) = o;
+        }
+        __syncthreads();
+    }
+}
+
 // FP64 block sum of one value per thread; result valid in thread 0.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double *red) {

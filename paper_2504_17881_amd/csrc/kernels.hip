@@ -199,13 +199,8 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
     };
     auto base_of = [&](uint64_t t) { return ((t ^ vt) << a.b) | (tid & ((1u << a.b) - 1u)); };
 
-    // all-ones masks of the thread index bits: a chunk's representative is
-    // then one AND-XOR per bit
     uint32_t tmask[B - M];
-#pragma unroll
-    for (int i = 0; i < B - M; ++i) tmask[i] = pin(0u - ((tid >> i) & 1u));
-    // LDS byte offsets: the XOR of indices commutes with the element shift
-    constexpr uint32_t SH = sizeof(Cx<T>) == 8 ? 3u : 4u;
+    tile_thread_masks<B - M>(tid, tmask);
 
     double sc = a.scale;
     if (renorm_in) sc *= *renorm_in;
@@ -244,36 +239,7 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
             for (int u = 0; u < PER; ++u) r[u] = psi[bn ^ a.uoff[u]];
         }
 
-        for (uint32_t c = 0; c < a.chunk_count; ++c) {
-            const ChunkRec ch = chunks[a.chunk_begin + c];
-            uint32_t k0 = 0;
-#pragma unroll
-            for (int i = 0; i < B - M; ++i) k0 ^= tmask[i] & ch.cvec[i];
-            const uint32_t k0b = k0 << SH;
-            uint32_t Xb[1 << M];
-            Xb[0] = 0;
-#pragma unroll
-            for (int v = 1; v < (1 << M); ++v)
-                Xb[v] = Xb[v & (v - 1)] ^ (ch.basis[__builtin_ctz(v)] << SH);
-            Cx<T> amp[1 << M];
-#pragma unroll
-            for (int v = 0; v < (1 << M); ++v)
-                amp[v] = *reinterpret_cast<const Cx<T> *>(lds_raw + (k0b ^ Xb[v]));
-            apply_rots<T, M>(amp, k0, tb, rots + ch.rot_begin, ch.rot_count);
-#pragma unroll
-            for (int v = 0; v < (1 << M); ++v) {
-                T f;
-                if constexpr (sizeof(T) == 4)
-                    f = ch.facf[v];
-                else
-                    f = ch.facd[v];
-                Cx<T> o;
-                o.re = amp[v].re * f;
-                o.im = amp[v].im * f;
-                *reinterpret_cast<Cx<T> *>(lds_raw + (k0b ^ Xb[v])) = o;
-            }
-            __syncthreads();
-        }
+        tile_chunks<T, B, M>(lds_raw, tmask, tb, chunks + a.chunk_begin, a.chunk_count, rots);
 
         {
             Cx<T> q[PER];

@@ -65,7 +65,11 @@ struct PlanCfg {
     bool commuting = false;
     bool span_only = false;  // batched plans: every pass is a span pass ...
     int pad_rank = 0;        // ... whose basis is padded to exactly this rank
+    bool tile_only = false;  // batched plans: every pass is a tile pass
 };
+
+// Kernel arguments of a tile pass of a plan for n qubits.
+void tile_args(int n, const Pass &ps, TileArgs &a);
 
 // Workspace regions (byte offsets, 256-aligned).
 struct WsLayout {

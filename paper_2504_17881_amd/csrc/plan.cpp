@@ -28,6 +28,7 @@
 #include <mutex>
 #include <new>
 #include <sstream>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -433,6 +434,27 @@ struct Builder {
         for (size_t p = P.begin; p < end; ++p) emit_plain(p);
     }
 
+    // Every pass a tile pass (batched tile rounds): from each position the
+    // virtual-qubit count that reaches furthest (one virtual qubit always
+    // takes at least one rotation).
+    void run_tile_only() {
+        size_t p = P.begin;
+        while (p < end) {
+            int gbest = -1;
+            size_t best = 0;
+            for (int g = 0; g <= cfg.max_virtual && g <= P.n - cfg.B && cfg.B - g >= kMinTileLow;
+                 ++g) {
+                const size_t f = tile_len(p, g);
+                if (f > best) {
+                    best = f;
+                    gbest = g;
+                }
+            }
+            if (gbest < 0) throw std::runtime_error("tile-only plan: no tile frame fits");
+            p = emit_tile(p, gbest);
+        }
+    }
+
     void run_span_only() {
         size_t p = P.begin;
         while (p < end) p = emit_span(p);
@@ -560,6 +582,29 @@ using namespace prx;
 
 namespace prx {
 
+void tile_args(int n, const Pass &ps, TileArgs &a) {
+    std::memset(&a, 0, sizeof(a));
+    for (int k = 0; k < ps.g; ++k) {
+        a.vmask[k] = ps.vmask[k];
+        a.tpivots |= (uint64_t)(ps.tpivot[k] & 63u) << (6 * k);
+    }
+    // slot u NT of the tile-set: tile (u NT) >> b, offset (u NT) mod 2^b
+    const uint32_t nt = 1u << (ps.B - ps.m);
+    for (uint32_t u = 0; u < (1u << ps.m); ++u) {
+        const uint32_t v = (u * nt) >> ps.b;
+        uint64_t c = 0;
+        for (int k = 0; k < ps.g; ++k)
+            if (v >> k & 1) c ^= ps.vmask[k];
+        a.uoff[u] = (c << ps.b) | ((u * nt) & ((1u << ps.b) - 1u));
+    }
+    a.n = n;
+    a.b = ps.b;
+    a.g = ps.g;
+    a.chunk_begin = (uint32_t)ps.c0;
+    a.chunk_count = (uint32_t)(ps.c1 - ps.c0);
+    a.scale = ps.scale;
+}
+
 static void default_cfg(prx_dtype dt, PlanCfg &c) {
     c.B = (dt == PRX_C64) ? 12 : 11;
     c.m = 4;
@@ -579,6 +624,7 @@ static void apply_opts(const prx_plan_opts *o, PlanCfg &c) {
     if (o->max_virtual) c.max_virtual = o->max_virtual < 0 ? 0 : o->max_virtual;
     if (o->renorm_every) c.renorm_every = o->renorm_every;
     if (o->commuting) c.commuting = o->commuting > 0;
+    if (o->tile_only) c.tile_only = o->tile_only > 0;
 }
 
 template <typename T>
@@ -622,8 +668,13 @@ static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtyp
         apply_opts(opts, P->cfg);
         if (internal) P->cfg = *internal;
         const bool fused = kernel != PRX_PLAIN;
+        if (P->cfg.tile_only && (!fused || n < P->cfg.B)) {
+            delete P;
+            return fail(PRX_ERR_INVALID, "tile_only needs a fused kernel and n >= tile_qubits");
+        }
         if (fused) {
-            if (!tile_supported(dtype, P->cfg.B, P->cfg.m) && P->n > P->cfg.B) {
+            if (!tile_supported(dtype, P->cfg.B, P->cfg.m) &&
+                (P->n > P->cfg.B || P->cfg.tile_only)) {
                 delete P;
                 return fail(PRX_ERR_UNSUPPORTED, "tile shape (tile_qubits, chunk_rank) not built");
             }
@@ -652,6 +703,8 @@ static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtyp
         // span passes need 2^(n - m) >= 1 cosets; tiny states fall back to plain
         if (P->cfg.span_only)
             bld.run_span_only();
+        else if (P->cfg.tile_only)
+            bld.run_tile_only();
         else if (!fused || n < 4)
             bld.run_plain();
         else {
@@ -696,6 +749,9 @@ static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtyp
     } catch (const std::bad_alloc &) {
         delete P;
         return fail(PRX_ERR_OOM, "out of host memory");
+    } catch (const std::runtime_error &e) {
+        delete P;
+        return fail(PRX_ERR_INVALID, e.what());
     }
     *out = P;
     return PRX_OK;
@@ -796,26 +852,7 @@ static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws
             e = launch_span(P->dtype, ps.m, psi, a, rots, rin, nout, s, &blocks);
         } else {
             TileArgs a;
-            std::memset(&a, 0, sizeof(a));
-            for (int k = 0; k < ps.g; ++k) {
-                a.vmask[k] = ps.vmask[k];
-                a.tpivots |= (uint64_t)(ps.tpivot[k] & 63u) << (6 * k);
-            }
-            // slot u NT of the tile-set: tile (u NT) >> b, offset (u NT) mod 2^b
-            const uint32_t nt = 1u << (ps.B - ps.m);
-            for (uint32_t u = 0; u < (1u << ps.m); ++u) {
-                const uint32_t v = (u * nt) >> ps.b;
-                uint64_t c = 0;
-                for (int k = 0; k < ps.g; ++k)
-                    if (v >> k & 1) c ^= ps.vmask[k];
-                a.uoff[u] = (c << ps.b) | ((u * nt) & ((1u << ps.b) - 1u));
-            }
-            a.n = P->n;
-            a.b = ps.b;
-            a.g = ps.g;
-            a.chunk_begin = (uint32_t)ps.c0;
-            a.chunk_count = (uint32_t)(ps.c1 - ps.c0);
-            a.scale = ps.scale;
+            tile_args(P->n, ps, a);
             e = launch_tile(P->dtype, ps.B, ps.m, psi, a, rots, chunks, rin, nout, s, &blocks);
         }
         if (e != hipSuccess) return hip_fail(e, "pass launch");

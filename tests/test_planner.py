@@ -200,3 +200,46 @@ def test_chunk_lanes_hit_distinct_lds_banks(dtype, bank_bits):
     P.prx_plan_destroy(pl)
     P.prx_sched_destroy(s)
     P.prx_ham_destroy(H)
+
+
+@pytest.mark.parametrize("n,dtype,B", [
+    (12, P.PRX_C64, 12), (15, P.PRX_C64, 12), (11, P.PRX_C128, 11), (14, P.PRX_C128, 11),
+])
+def test_tile_only_plans_of_batched_samples(n, dtype, B):
+    """The form batched samples take: qDRIFT draws in random order, every pass
+    a tile pass (B tile qubits, rank-4 chunks, up to 8 virtual qubits, no
+    renormalisation), reproducing the oracle through the interpreter."""
+    x, z, h = synth.jw_hamiltonian(n, 80, 1000 + n)
+    H = P.prx_ham_create(n, x, z, h)
+    s = P.prx_sched_qdrift(H, 1.0, 400, n)
+    _, rx, rz, rp = P.prx_sched_view(s)
+    opts = dict(tile_qubits=B, chunk_rank=4, max_fuse=128, max_virtual=8, renorm_every=-1,
+                tile_only=1)
+    pl = P.prx_plan_create(s, n, dtype, 0, len(rx), P.PRX_FUSED, opts)
+    info = P.prx_plan_get_info(pl)
+    assert info["tile_passes"] == info["passes"] > 0
+    for pi in range(info["passes"]):
+        ps = P.prx_plan_pass(pl, pi)
+        assert ps["g"] <= min(8, n - B) and ps["b"] == B - ps["g"]
+    _check_composition(pl, rx, rz, rp)
+    _check_closure(pl, n)
+    psi0 = synth.gaussian_state(n, 5)
+    ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+    out = run_plan(pl, psi0, n)
+    tol = 1e-11 if dtype == P.PRX_C128 else 5e-5
+    assert np.linalg.norm(out - ref) <= tol
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
+
+
+def test_tile_only_rejects_small_states_and_plain_kernel():
+    n = 10
+    x, z, phi = synth.random_pauli_rotations(n, 20, seed=3)
+    s = _sched(n, x, z, phi)
+    for kernel, opts in [(P.PRX_FUSED, dict(tile_only=1)),
+                         (P.PRX_PLAIN, dict(tile_only=1, tile_qubits=10))]:
+        with pytest.raises(P.PrxError) as e:
+            P.prx_plan_create(s, n, P.PRX_C64, 0, 20, kernel, opts)
+        assert e.value.status == P.PRX_ERR_INVALID
+    P.prx_sched_destroy(s)
