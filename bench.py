@@ -153,6 +153,82 @@ def fusion_sweep(ns, reps: int) -> int:
     return 0
 
 
+def batch_workload(steps: int, warmup: int) -> int:
+    """The batching workload: 256 qDRIFT samples with n uniform on 16..24
+    (per-size JW Hamiltonian, L = 500, N = 2000 draws, t = 1), complex64,
+    basis initial states, all samples in one captured graph.  A step is one
+    graph launch (every sample's full sequence and the overlap read-out),
+    timed with HIP events on its stream; the states are reset between
+    steps, outside the timed region.  One JSON line: samples/s, and the
+    algorithmic HBM traffic (every pass reads and writes its sample once)
+    against the 8 TB/s peak."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    import synth
+    from paper_2504_17881_amd import prx as P
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS["qdrift_batch"]
+    ns = synth.batch_qubit_counts(w["S"], w["n_lo"], w["n_hi"], w["n_seed"])
+    hams, scheds = {}, []
+    for i, n in enumerate(ns):
+        if n not in hams:
+            x, z, h = synth.jw_hamiltonian(n, w["L"], 1000 + n)
+            hams[n] = P.prx_ham_create(n, x, z, h)
+        scheds.append(P.prx_sched_qdrift(hams[n], w["t"], w["N"], i))
+    basis = [synth.basis_index(n) for n in ns]
+    psis = [torch.zeros(1 << n, dtype=torch.complex64, device=dev) for n in ns]
+    b = P.prx_batch_create(ns, scheds, P.PRX_C64, basis)
+    info = P.prx_batch_get_info(b)
+    ws = torch.empty(P.prx_batch_workspace_bytes(b), dtype=torch.uint8, device=dev)
+    ovd = torch.zeros(2 * len(ns), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    P.prx_batch_upload(b, psis, ws, stream=stream)
+    g = P.prx_batch_graph(b, ws, ovd, stream)
+    print(f"[bench] qdrift batch: S={len(ns)} rounds={info['rounds']} passes={info['passes']} "
+          f"tile samples={info['tile_samples']}", file=sys.stderr, flush=True)
+    total_ms = 0.0
+    for it in range(warmup + steps):
+        for t, k in zip(psis, basis):
+            t.zero_()
+            t[k] = 1.0
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.prx_graph_launch(g, stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1)
+        if it >= warmup:
+            total_ms += ms
+        print(f"[bench] batch step {it} ({'warm-up' if it < warmup else 'timed'}): {ms:.1f} ms",
+              file=sys.stderr, flush=True)
+    ov = ovd.cpu().numpy()
+    ms = total_ms / max(1, steps)
+    gbs = 2.0 * info["amp_sweeps"] * 8 / (ms * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "qDRIFT batch throughput (256 samples, n 16-24, N = 2000, complex64)",
+        "value": len(ns) / (ms * 1e-3), "unit": "samples/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "qdrift_batch", "S": len(ns), "n_lo": w["n_lo"],
+                   "n_hi": w["n_hi"], "L": w["L"], "N": w["N"], "t": w["t"],
+                   "tile_samples": info["tile_samples"], "rounds": info["rounds"],
+                   "passes": info["passes"], "amp_sweeps": info["amp_sweeps"]},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "kernel": "whole graph (all rounds)"},
+        "mean_overlap": [float(np.mean(ov[0::2])), float(np.mean(ov[1::2]))],
+    }), flush=True)
+    P.prx_graph_destroy(g)
+    P.prx_batch_destroy(b)
+    for s in scheds:
+        P.prx_sched_destroy(s)
+    for H in hams.values():
+        P.prx_ham_destroy(H)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +254,9 @@ def main() -> int:
                     help="instead of the benchmark, print the fusion-depth curve (plain against "
                          "fused for groups of 1, 10, 100 rotations sharing a high X part)")
     ap.add_argument("--sweep-n", default="16,20,24,28,32")
+    ap.add_argument("--batch-workload", action="store_true",
+                    help="instead of the benchmark, time the qDRIFT batching workload "
+                         "(256 samples in one graph)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path is a "
@@ -185,6 +264,8 @@ def main() -> int:
         return 2
     if args.fusion_sweep:
         return fusion_sweep([int(v) for v in args.sweep_n.split(",")], max(1, args.steps))
+    if args.batch_workload:
+        return batch_workload(max(1, args.steps), max(0, args.warmup))
 
     import numpy as np
     import torch

@@ -323,6 +323,17 @@ typedef struct prx_graph prx_graph;
 prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sched,
                             prx_dtype dtype, const uint64_t *basis_idx, prx_batch **out);
 size_t prx_batch_workspace_bytes(const prx_batch *b);
+/* Summary of a batch plan. */
+typedef struct {
+    size_t samples;       /* S */
+    size_t tile_samples;  /* samples planned into tile passes */
+    size_t rounds;        /* largest pass count */
+    size_t passes;        /* passes summed over the samples */
+    double amp_sweeps;    /* sum over samples of passes * 2^n: each sweep reads and
+                             writes every amplitude once (algorithmic bytes
+                             = 2 * amp_sweeps * bytes per amplitude) */
+} prx_batch_info;
+prx_status prx_batch_get_info(const prx_batch *b, prx_batch_info *out);
 /* Records the device state pointers psi[s] (host array of S distinct,
  * non-overlapping, 16-byte aligned buffers) and copies the batch tables into
  * `ws`; waits for the copies. */

@@ -377,6 +377,23 @@ prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sche
 
 size_t prx_batch_workspace_bytes(const prx_batch *b) { return b ? b->total : 0; }
 
+prx_status prx_batch_get_info(const prx_batch *b, prx_batch_info *out) {
+    if (!b || !out) return fail(PRX_ERR_INVALID, "null pointer");
+    std::memset(out, 0, sizeof(*out));
+    out->samples = b->S;
+    out->tile_samples = b->tsamples.size();
+    out->rounds = b->rounds;
+    for (const BSample &s : b->samples) {
+        out->passes += s.pass_count;
+        out->amp_sweeps += (double)s.pass_count * std::ldexp(1.0, (int)s.n);
+    }
+    for (const BTSample &s : b->tsamples) {
+        out->passes += s.pass_count;
+        out->amp_sweeps += (double)s.pass_count * std::ldexp(1.0, (int)s.n);
+    }
+    return PRX_OK;
+}
+
 prx_status prx_batch_upload(prx_batch *b, void *const *psi, void *ws, size_t ws_bytes,
                             void *stream) {
     if (!b || !psi || !ws) return fail(PRX_ERR_INVALID, "null pointer");

@@ -136,6 +136,7 @@ _sig("prx_renormalize", _st, _vp, _i, _i, _vp, _sz, _vp)
 _sig("prx_batch_create", _st, _sz, ctypes.POINTER(_i), ctypes.POINTER(_vp), _i, _u64p,
      ctypes.POINTER(_vp))
 _sig("prx_batch_workspace_bytes", _sz, _vp)
+_sig("prx_batch_get_info", _st, _vp, _vp)
 _sig("prx_batch_upload", _st, _vp, ctypes.POINTER(_vp), _vp, _sz, _vp)
 _sig("prx_batch_execute", _st, _vp, _vp, _sz, _vp, _vp)
 _sig("prx_batch_check", _st, _vp, _vp, _vp)
@@ -426,6 +427,17 @@ def prx_batch_create(n_list, scheds, dtype: int, basis_idx) -> int:
 
 def prx_batch_workspace_bytes(batch: int) -> int:
     return int(_lib.prx_batch_workspace_bytes(batch))
+
+
+class prx_batch_info(ctypes.Structure):
+    _fields_ = [("samples", _sz), ("tile_samples", _sz), ("rounds", _sz), ("passes", _sz),
+                ("amp_sweeps", ctypes.c_double)]
+
+
+def prx_batch_get_info(batch: int) -> dict:
+    o = prx_batch_info()
+    _check(_lib.prx_batch_get_info(batch, ctypes.byref(o)))
+    return {f: getattr(o, f) for f, _ in prx_batch_info._fields_}
 
 
 def prx_batch_upload(batch: int, psis, ws, stream=None, ws_bytes=None) -> None:

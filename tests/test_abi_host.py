@@ -209,3 +209,46 @@ def test_batch_create_host_checks():
         P.prx_sched_destroy(s)
     for H in hams:
         P.prx_ham_destroy(H)
+
+
+@pytest.mark.parametrize("dtype,B", [(P.PRX_C64, 12), (P.PRX_C128, 11)])
+def test_batch_info_splits_samples_by_tile_frame(dtype, B):
+    """Samples of at least B qubits are planned as tile-only plans with the
+    batch's fixed options; the rest into span passes."""
+    ns = [6, 10, 11, 12, 13]
+    hams, scheds = [], []
+    for i, n in enumerate(ns):
+        x, z, h = synth.jw_hamiltonian(n, 40, 1000 + n)
+        H = P.prx_ham_create(n, x, z, h)
+        hams.append(H)
+        scheds.append(P.prx_sched_qdrift(H, 1.0, 150, i))
+    basis = [synth.basis_index(n) for n in ns]
+    b = P.prx_batch_create(ns, scheds, dtype, basis)
+    info = P.prx_batch_get_info(b)
+    P.prx_batch_destroy(b)
+    assert info["samples"] == len(ns)
+    assert info["tile_samples"] == sum(n >= B for n in ns)
+    opts = dict(tile_qubits=B, chunk_rank=4, max_fuse=128, max_virtual=8, renorm_every=-1,
+                tile_only=1)
+    tile_passes, tile_sweeps, counts = 0, 0.0, []
+    for n, s in zip(ns, scheds):
+        if n < B:
+            continue
+        pl = P.prx_plan_create(s, n, dtype, 0, 150, P.PRX_FUSED, opts)
+        k = P.prx_plan_get_info(pl)["passes"]
+        P.prx_plan_destroy(pl)
+        tile_passes += k
+        tile_sweeps += k * 2.0 ** n
+        counts.append(k)
+    assert info["passes"] > tile_passes
+    assert info["rounds"] >= max(counts)
+    span_sweeps = info["amp_sweeps"] - tile_sweeps
+    span_passes = info["passes"] - tile_passes
+    small = [n for n in ns if n < B]
+    # every span sample's sweeps are whole multiples of its size
+    assert min(2.0 ** n for n in small) * span_passes <= span_sweeps
+    assert span_sweeps <= max(2.0 ** n for n in small) * span_passes
+    for s in scheds:
+        P.prx_sched_destroy(s)
+    for H in hams:
+        P.prx_ham_destroy(H)
