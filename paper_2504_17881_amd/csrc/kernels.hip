@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(256) k_span(Cx<T> *__restrict__ psi, SpanArgs 
     pending_factors<M>(F, a.fscale);
     double nrm = 0.0;
     if (live) {
+        T part = 0;  // the thread's 2^M squares in the state's precision
 #pragma unroll
         for (int v = 0; v < (1 << M); ++v) {
             const T s = (T)(sc * F[v]);
@@ -140,8 +141,10 @@ __global__ void __launch_bounds__(256) k_span(Cx<T> *__restrict__ psi, SpanArgs 
             o.re = amp[v].re * s;
             o.im = amp[v].im * s;
             psi[k0 ^ X[v]] = o;
-            nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+            part = fma(o.re, o.re, part);
+            part = fma(o.im, o.im, part);
         }
+        nrm = (double)part;
     }
     if (norm_out) {
         nrm = block_sum<256>(nrm, red);
@@ -245,14 +248,17 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
             Cx<T> q[PER];
 #pragma unroll
             for (int u = 0; u < PER; ++u) q[u] = lds[tid + (uint32_t)u * NT];
+            T part = 0;  // the thread's PER squares in the state's precision
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 Cx<T> o = q[u];
                 o.re *= s;
                 o.im *= s;
                 psi[base ^ a.uoff[u]] = o;
-                nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+                part = fma(o.re, o.re, part);
+                part = fma(o.im, o.im, part);
             }
+            nrm += (double)part;
         }
         if (next) {
             __syncthreads();  // every thread has read the finished set
