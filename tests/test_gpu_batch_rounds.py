@@ -1,5 +1,6 @@
-"""GPU tests of the batched path: one grid-stride kernel per pass round over
-all samples' slices (no cross-workgroup waits), captured as one graph."""
+"""GPU tests of the batched path: per pass round, one kernel over the tile-set
+items of the samples planned into tile passes and one over the coset slices
+of the smaller samples (no cross-workgroup waits), captured as one graph."""
 import math
 import time
 
@@ -55,6 +56,40 @@ def test_rounds_match_oracle_per_sample(dtype):
     for i, n in enumerate(ns):
         x, z, h, _ = hams[n]
         rx, rz, rp = S.qdrift(x, z, h, 1.0, N, i)
+        psi0 = np.zeros(1 << n, dtype=np.complex128)
+        psi0[basis[i]] = 1
+        ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+        assert rel_err(to_host(psis[i]), ref) <= tol, (i, n)
+        assert abs(complex(ov[2 * i], ov[2 * i + 1]) - ref[basis[i]]) <= max(tol, 1e-12)
+    P.prx_batch_destroy(b)
+    _free(hams, scheds)
+
+
+@pytest.mark.parametrize("dtype", [P.PRX_C64, P.PRX_C128])
+def test_tile_rounds_with_many_virtual_qubits(dtype):
+    """Larger samples (tile passes with up to 9 virtual qubits at complex64, 7
+    at complex128) of uneven pass counts next to span samples, checked
+    element by element against the oracle."""
+    ns = [13, 17, 20, 10, 18, 11]
+    N = 500
+    hams, scheds = _inputs(ns, 120, N, 0.8, seed0=77)
+    basis = [synth.basis_index(n) for n in ns]
+    psis = [basis_state(n, b, dtype) for n, b in zip(ns, basis)]
+    b = P.prx_batch_create(ns, scheds, dtype, basis)
+    info = P.prx_batch_get_info(b)
+    assert info["tile_samples"] == sum(n >= (13 if dtype == P.PRX_C64 else 11) for n in ns)
+    ws = workspace(P.prx_batch_workspace_bytes(b))
+    ovd = torch.zeros(2 * len(ns), dtype=torch.float64, device=dev())
+    P.prx_batch_upload(b, psis, ws)
+    print(f"[tile rounds dtype={dtype}] rounds={info['rounds']} launching", flush=True)
+    P.prx_batch_execute(b, ws, ovd)
+    P.prx_batch_check(b, ws)
+    print(f"[tile rounds dtype={dtype}] done", flush=True)
+    ov = ovd.cpu().numpy()
+    tol = 1e-12 if dtype == P.PRX_C128 else 8 * EPS32 * math.sqrt(N) + 1e-6
+    for i, n in enumerate(ns):
+        x, z, h, _ = hams[n]
+        rx, rz, rp = S.qdrift(x, z, h, 0.8, N, 77 + i)
         psi0 = np.zeros(1 << n, dtype=np.complex128)
         psi0[basis[i]] = 1
         ref = sv.c_apply_rotations(psi0, rx, rz, rp)
