@@ -99,6 +99,67 @@ def test_tile_rounds_with_many_virtual_qubits(dtype):
     _free(hams, scheds)
 
 
+def _empty_sched(n):
+    e = np.array([], dtype=np.uint64)
+    return P.prx_sched_from_rotations(n, e, e, np.array([], dtype=np.float64))
+
+
+def test_rounds_with_empty_schedules():
+    """Samples with no rotations stay untouched next to a tile sample and a
+    span sample; a batch of empty samples only reads the overlaps."""
+    dtype = P.PRX_C64
+    ns = [14, 13, 9, 8]
+    N = 80
+    x13, z13, h13 = synth.jw_hamiltonian(13, 40, 1013)
+    x9, z9, h9 = synth.jw_hamiltonian(9, 40, 1009)
+    H13 = P.prx_ham_create(13, x13, z13, h13)
+    H9 = P.prx_ham_create(9, x9, z9, h9)
+    scheds = [_empty_sched(14), P.prx_sched_qdrift(H13, 0.6, N, 5),
+              P.prx_sched_qdrift(H9, 0.6, N, 6), _empty_sched(8)]
+    basis = [synth.basis_index(n) for n in ns]
+    psis = [basis_state(n, k, dtype) for n, k in zip(ns, basis)]
+    b = P.prx_batch_create(ns, scheds, dtype, basis)
+    info = P.prx_batch_get_info(b)
+    assert info["tile_samples"] == 2 and info["rounds"] > 0
+    ws = workspace(P.prx_batch_workspace_bytes(b))
+    ovd = torch.zeros(2 * len(ns), dtype=torch.float64, device=dev())
+    P.prx_batch_upload(b, psis, ws)
+    print(f"[empty samples] rounds={info['rounds']} launching", flush=True)
+    P.prx_batch_execute(b, ws, ovd)
+    P.prx_batch_check(b, ws)
+    print("[empty samples] done", flush=True)
+    ov = ovd.cpu().numpy()
+    tol = 8 * EPS32 * math.sqrt(N) + 1e-6
+    for i, (n, (x, z, h), seed) in [(1, (13, (x13, z13, h13), 5)), (2, (9, (x9, z9, h9), 6))]:
+        rx, rz, rp = S.qdrift(x, z, h, 0.6, N, seed)
+        psi0 = np.zeros(1 << n, dtype=np.complex128)
+        psi0[basis[i]] = 1
+        ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+        assert rel_err(to_host(psis[i]), ref) <= tol, (i, n)
+    for i in (0, 3):
+        out = to_host(psis[i])
+        assert out[basis[i]] == 1 and np.count_nonzero(out) == 1
+        assert ov[2 * i] == 1.0 and ov[2 * i + 1] == 0.0
+    P.prx_batch_destroy(b)
+    # only empty samples: no round kernels, the overlaps still arrive
+    e_scheds = [_empty_sched(14), _empty_sched(8)]
+    e_ns, e_basis = [14, 8], [basis[0], basis[3]]
+    e_psis = [basis_state(n, k, dtype) for n, k in zip(e_ns, e_basis)]
+    b = P.prx_batch_create(e_ns, e_scheds, dtype, e_basis)
+    assert P.prx_batch_get_info(b)["rounds"] == 0
+    ws = workspace(P.prx_batch_workspace_bytes(b))
+    ovd = torch.zeros(4, dtype=torch.float64, device=dev())
+    P.prx_batch_upload(b, e_psis, ws)
+    P.prx_batch_execute(b, ws, ovd)
+    P.prx_batch_check(b, ws)
+    assert ovd.cpu().numpy().tolist() == [1.0, 0.0, 1.0, 0.0]
+    P.prx_batch_destroy(b)
+    for sc in scheds + e_scheds:
+        P.prx_sched_destroy(sc)
+    P.prx_ham_destroy(H13)
+    P.prx_ham_destroy(H9)
+
+
 def test_rounds_one_call_and_graph_replay():
     dtype = P.PRX_C64
     ns = [8, 11, 16, 9, 12]

@@ -127,6 +127,32 @@ def test_trotter1_n32_c64_fused_against_c128_plain_prefix():
     P.prx_ham_destroy(H)
 
 
+def test_trotter1_n32_c64_tuned_launch_against_c128_plain_prefix():
+    """The benchmark's own launch configuration: the committed autotune cache
+    selects 14-qubit persistent tile-sets with up to 10 virtual qubits for
+    n = 32 complex64 (PRX_AUTO), checked on rotations 2500..3499 of the
+    benchmark schedule (the step's high-qubit terms, where the passes use
+    most virtual qubits) against the complex128 one-rotation sweep."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    P.prx_autotune_load(os.path.join(root, "paper_2504_17881_amd", "tuning", "gfx950.json"))
+    H, s = _jw_sched(32, 5000, 0, 1, 0.5, 4, True)
+    k0 = synth.basis_index(32)
+    r0, R = 2500, 1000
+    a = basis_state(32, k0, P.PRX_C64)
+    info = apply(a, 32, P.PRX_C64, s, P.PRX_AUTO, r0, r0 + R)
+    assert info["tile_qubits"] == 14 and info["tile_passes"] == info["passes"]
+    b = basis_state(32, k0, P.PRX_C128)
+    apply(b, 32, P.PRX_C128, s, P.PRX_PLAIN, r0, r0 + R)
+    d = _diff_norm(a, b)
+    oa = P.prx_amplitude(a, 32, P.PRX_C64, k0)
+    ob = P.prx_amplitude(b, 32, P.PRX_C128, k0)
+    print(f"[n32 tuned prefix {R}] passes {info['passes']} err_l2 = {d:.3e}, "
+          f"|d overlap| = {abs(oa - ob):.3e}", flush=True)
+    assert d <= 8 * EPS32 * math.sqrt(R) and abs(oa - ob) <= 1e-4
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
+
+
 def _partial(n):
     x, z, h = synth.jw_hamiltonian(n, 8200, 0)
     H = P.prx_ham_create(n, x, z, h)
