@@ -247,6 +247,9 @@ def main() -> int:
                          "save its cache to this path")
     ap.add_argument("--tune-rotations", type=int, default=5000,
                     help="rotations of the schedule timed per autotune setting (default: one Trotter step)")
+    ap.add_argument("--tune-dtype", choices=("c64", "c128"), default="c64",
+                    help="state precision the autotuner times (the saved cache keeps the other "
+                         "entries of --tune-cache)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="GIB",
                     help="first run torch copies of GIB GiB (3 launches): the known-size "
                          "reference that scales hardware byte counters")
@@ -298,26 +301,28 @@ def main() -> int:
 
     # ---------------- planner settings: tuned cache (or a fresh tuning run)
     tuned = None
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        P.prx_autotune_load(args.tune_cache)
     if args.autotune_save:
-        print("[bench] autotuning", file=sys.stderr, flush=True)
+        print(f"[bench] autotuning {args.tune_dtype}", file=sys.stderr, flush=True)
         R = min(args.tune_rotations, len(sx))
         sub = P.prx_sched_from_rotations(n, sx[:R], sz[:R], sphi[:R])
-        scratch = torch.zeros(1 << n, dtype=torch.complex64, device=dev)
+        tdt = P.PRX_C64 if args.tune_dtype == "c64" else P.PRX_C128
+        scratch = torch.zeros(1 << n, dtype=torch.complex64 if tdt == P.PRX_C64
+                              else torch.complex128, device=dev)
         scratch[k0] = 1.0
         tws = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         def _trial(o, ms):
             print(f"[bench] tune {({k: v for k, v in o.items() if v})} {ms:.1f} ms",
                   file=sys.stderr, flush=True)
-        tuned, trials = P.prx_autotune(scratch, n, P.PRX_C64, sub, tws, progress=_trial)
+        best, trials = P.prx_autotune(scratch, n, tdt, sub, tws, progress=_trial)
         os.makedirs(os.path.dirname(os.path.abspath(args.autotune_save)), exist_ok=True)
         P.prx_autotune_save(args.autotune_save)
-        print(f"[bench] autotune: {trials} trials, best {tuned}", file=sys.stderr, flush=True)
+        print(f"[bench] autotune: {trials} trials, best {best}", file=sys.stderr, flush=True)
         P.prx_sched_destroy(sub)
         del scratch, tws
         torch.cuda.empty_cache()
-    elif args.tune_cache and os.path.exists(args.tune_cache):
-        P.prx_autotune_load(args.tune_cache)
-        tuned = P.prx_autotune_lookup(n, P.PRX_C64)
+    tuned = P.prx_autotune_lookup(n, P.PRX_C64)
     kernel = P.PRX_AUTO if tuned else P.PRX_FUSED
 
     # ---------------- fused complex64: one plan per Trotter step (identical steps)
