@@ -59,25 +59,52 @@ struct BatchArgs {
     const uint32_t *order;        // sorted position -> sample
 };
 
+// State amplitudes addressed as global memory: the states' addresses come
+// from the sample tables, and without the address space the compiler would
+// use flat accesses, which also count against the LDS/scalar wait counter.
+template <typename T>
+using V2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ Cx<T> gload(uint64_t psi, uint64_t i) {
+    const V2<T> v = ((const __attribute__((address_space(1))) V2<T> *)psi)[i];
+    Cx<T> r;
+    r.re = v.x;
+    r.im = v.y;
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(uint64_t psi, uint64_t i, const Cx<T> &a) {
+    V2<T> v;
+    v.x = a.re;
+    v.y = a.im;
+    ((__attribute__((address_space(1))) V2<T> *)psi)[i] = v;
+}
+
 // Round p: items j in [0, prefixQ[active]) over the first `active` sorted
 // samples; item j is slice j - prefixQ[k] of sorted sample k.
+// The tables arrive as separate __restrict__ arguments: the compiler then
+// knows the state stores cannot change them and reads them with scalar
+// loads, so the rotation loop's control values stay uniform.
 template <typename T>
-__global__ void __launch_bounds__(256) k_batch_round(BatchArgs a, uint32_t p, uint32_t active,
-                                                     uint64_t items) {
+__global__ void __launch_bounds__(256)
+    k_batch_round(const BSample *__restrict__ samples, const BPass *__restrict__ passes,
+                  const void *__restrict__ rot_table, const uint64_t *__restrict__ prefixQ,
+                  const uint32_t *__restrict__ order, uint32_t p, uint32_t active,
+                  uint64_t items) {
     constexpr int M = kBatchRank;
     for (uint64_t j = blockIdx.x; j < items; j += gridDim.x) {
         // last k < active with prefixQ[k] <= j (uniform across the block)
         uint32_t lo = 0, hi = active;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (a.prefixQ[mid] <= j) lo = mid; else hi = mid;
+            if (prefixQ[mid] <= j) lo = mid; else hi = mid;
         }
-        const uint32_t s = a.order[lo];
-        const uint64_t q = j - a.prefixQ[lo];
-        const BSample smp = a.samples[s];
-        const BPass ps = a.passes[smp.pass_begin + p];
-        Cx<T> *psi = reinterpret_cast<Cx<T> *>(smp.psi);
-        const RotRec<T> *rots = reinterpret_cast<const RotRec<T> *>(a.rots) + ps.rot_begin;
+        const uint32_t s = order[lo];
+        const uint64_t q = j - prefixQ[lo];
+        const BSample smp = samples[s];
+        const BPass ps = passes[smp.pass_begin + p];
+        const uint64_t psi = smp.psi;
+        const RotRec<T> *rots = reinterpret_cast<const RotRec<T> *>(rot_table) + ps.rot_begin;
         uint64_t X[1 << M];
         X[0] = 0;
 #pragma unroll
@@ -95,14 +122,14 @@ __global__ void __launch_bounds__(256) k_batch_round(BatchArgs a, uint32_t p, ui
             for (int i = 0; i < M; ++i) k0 = insert_zero64(k0, ps.pivot[i]);
             Cx<T> amp[1 << M];
 #pragma unroll
-            for (int v = 0; v < (1 << M); ++v) amp[v] = psi[k0 ^ X[v]];
+            for (int v = 0; v < (1 << M); ++v) amp[v] = gload<T>(psi, k0 ^ X[v]);
             apply_rots<T, M>(amp, k0, 0, rots, ps.rot_count);
 #pragma unroll
             for (int v = 0; v < (1 << M); ++v) {
                 Cx<T> o;
                 o.re = amp[v].re * sc[v];
                 o.im = amp[v].im * sc[v];
-                psi[k0 ^ X[v]] = o;
+                gstore<T>(psi, k0 ^ X[v], o);
             }
         }
     }
@@ -127,7 +154,10 @@ struct BatchTileArgs {
 
 template <typename T, int B, int M>
 __global__ void __launch_bounds__(1 << (B - M))
-    k_batch_tile_round(BatchTileArgs a, uint32_t p, uint32_t active, uint64_t items) {
+    k_batch_tile_round(const BTSample *__restrict__ samples, const TileArgs *__restrict__ passes,
+                       const ChunkRec *__restrict__ chunks, const void *__restrict__ rot_table,
+                       const uint64_t *__restrict__ prefixW, const uint32_t *__restrict__ order,
+                       uint32_t p, uint32_t active, uint64_t items) {
     constexpr int NT = 1 << (B - M);
     constexpr int PER = 1 << M;
     __shared__ __align__(16) Cx<T> lds[1 << B];
@@ -140,12 +170,12 @@ __global__ void __launch_bounds__(1 << (B - M))
         uint32_t lo = 0, hi = active;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (a.prefixW[mid] <= j) lo = mid; else hi = mid;
+            if (prefixW[mid] <= j) lo = mid; else hi = mid;
         }
-        const BTSample smp = a.samples[a.order[lo]];
-        const uint32_t w = (uint32_t)(j - a.prefixW[lo]);
-        const TileArgs *ta = a.passes + smp.pass_begin + p;
-        Cx<T> *psi = reinterpret_cast<Cx<T> *>(smp.psi);
+        const BTSample smp = samples[order[lo]];
+        const uint32_t w = (uint32_t)(j - prefixW[lo]);
+        const TileArgs *ta = passes + smp.pass_begin + p;
+        const uint64_t psi = smp.psi;
         // the set's base tile and this thread's slots (see k_tile)
         const int b = ta->b, g = ta->g;
         uint64_t tb = w;
@@ -158,13 +188,13 @@ __global__ void __launch_bounds__(1 << (B - M))
         {
             Cx<T> r[PER];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) r[u] = psi[base ^ ta->uoff[u]];
+            for (int u = 0; u < PER; ++u) r[u] = gload<T>(psi, base ^ ta->uoff[u]);
 #pragma unroll
             for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
         }
         __syncthreads();
-        tile_chunks<T, B, M>(lds_raw, tmask, tb, a.chunks + ta->chunk_begin, ta->chunk_count,
-                             reinterpret_cast<const RotRec<T> *>(a.rots));
+        tile_chunks<T, B, M>(lds_raw, tmask, tb, chunks + ta->chunk_begin, ta->chunk_count,
+                             reinterpret_cast<const RotRec<T> *>(rot_table));
         const T s = (T)ta->scale;
         {
             Cx<T> q[PER];
@@ -175,7 +205,7 @@ __global__ void __launch_bounds__(1 << (B - M))
                 Cx<T> o = q[u];
                 o.re *= s;
                 o.im *= s;
-                psi[base ^ ta->uoff[u]] = o;
+                gstore<T>(psi, base ^ ta->uoff[u], o);
             }
         }
         __syncthreads();  // the next item overwrites the LDS
@@ -473,10 +503,12 @@ prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
             const unsigned grid = (unsigned)std::min<uint64_t>(titems, kTileGridCap);
             if (b->dtype == PRX_C64)
                 hipLaunchKernelGGL((k_batch_tile_round<float, 13, kBatchTileM>), dim3(grid),
-                                   dim3(tile_threads), 0, st, ta, p, tactive, titems);
+                                   dim3(tile_threads), 0, st, ta.samples, ta.passes, ta.chunks,
+                                   ta.rots, ta.prefixW, ta.order, p, tactive, titems);
             else
                 hipLaunchKernelGGL((k_batch_tile_round<double, 11, kBatchTileM>), dim3(grid),
-                                   dim3(tile_threads), 0, st, ta, p, tactive, titems);
+                                   dim3(tile_threads), 0, st, ta.samples, ta.passes, ta.chunks,
+                                   ta.rots, ta.prefixW, ta.order, p, tactive, titems);
             PRX_HIP(hipGetLastError());
         }
         const uint32_t active = b->round_active[p];
@@ -484,11 +516,11 @@ prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
         if (items) {
             const unsigned grid = (unsigned)std::min<uint64_t>(items, cap);
             if (b->dtype == PRX_C64)
-                hipLaunchKernelGGL(k_batch_round<float>, dim3(grid), dim3(256), 0, st, a, p,
-                                   active, items);
+                hipLaunchKernelGGL(k_batch_round<float>, dim3(grid), dim3(256), 0, st, a.samples,
+                                   a.passes, a.rots, a.prefixQ, a.order, p, active, items);
             else
-                hipLaunchKernelGGL(k_batch_round<double>, dim3(grid), dim3(256), 0, st, a, p,
-                                   active, items);
+                hipLaunchKernelGGL(k_batch_round<double>, dim3(grid), dim3(256), 0, st, a.samples,
+                                   a.passes, a.rots, a.prefixQ, a.order, p, active, items);
             PRX_HIP(hipGetLastError());
         }
     }

@@ -245,6 +245,27 @@ __device__ __forceinline__ void rot_slot_any(Cx<T> (&amp)[1 << M], T ga, T gb, u
         rot_slot<T, M, I, false>(amp, ga, gb, zeta);
 }
 
+// The complex64 rank-4 variants as one jump table (rot_jump_f32m4.inc,
+// written by gen_rot_jump.py): a computed jump to variant var (< 64) of
+// equal-sized blocks instead of a 7-level branch tree.  var is uniform (one
+// rotation record per wave); the table clamps it to 63.
+#include "rot_jump_f32m4.inc"
+__device__ __forceinline__ void rot_jump(Cx<float> (&amp)[16], float ga, float gb, uint32_t var) {
+    uint32_t t;
+    asm(PRX_ROT_JUMP_F32M4
+        : "+v"(amp[0].re), "+v"(amp[0].im), "+v"(amp[1].re), "+v"(amp[1].im),
+          "+v"(amp[2].re), "+v"(amp[2].im), "+v"(amp[3].re), "+v"(amp[3].im),
+          "+v"(amp[4].re), "+v"(amp[4].im), "+v"(amp[5].re), "+v"(amp[5].im),
+          "+v"(amp[6].re), "+v"(amp[6].im), "+v"(amp[7].re), "+v"(amp[7].im),
+          "+v"(amp[8].re), "+v"(amp[8].im), "+v"(amp[9].re), "+v"(amp[9].im),
+          "+v"(amp[10].re), "+v"(amp[10].im), "+v"(amp[11].re), "+v"(amp[11].im),
+          "+v"(amp[12].re), "+v"(amp[12].im), "+v"(amp[13].re), "+v"(amp[13].im),
+          "+v"(amp[14].re), "+v"(amp[14].im), "+v"(amp[15].re), "+v"(amp[15].im),
+          "=&s"(t)
+        : "v"(ga), "v"(gb), "s"(__builtin_amdgcn_readfirstlane(var))
+        : "s90", "s91", "scc");
+}
+
 // Binary dispatch of a static-sign rotation on the uniform variant index
 // var = slot 2^M + imag 2^(M-1) + zp in [LO, HI); var = M 2^M is the
 // diagonal (x = 0) rotation.
@@ -307,7 +328,15 @@ __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t
                 ga = pin(flip_add(rec.tau_a, cnt));
                 gb = pin(flip_add(rec.tau_b, cnt));
             }
-            rot_var<T, M, 0, (M << M) + 1>(amp, ga, gb, (rec.info >> 16) & 0xffu, zeta);
+            const uint32_t var = (rec.info >> 16) & 0xffu;
+            if constexpr (sizeof(T) == 4 && M == 4) {
+                if (var == (uint32_t)(M << M))
+                    rot_diag<T, M>(amp, ga, zeta);
+                else
+                    rot_jump(amp, ga, gb, var);
+            } else {
+                rot_var<T, M, 0, (M << M) + 1>(amp, ga, gb, var, zeta);
+            }
             continue;
         }
         const T ga = pin(flip(rec.tau_a, s0));

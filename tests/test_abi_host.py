@@ -252,3 +252,30 @@ def test_batch_info_splits_samples_by_tile_frame(dtype, B):
         P.prx_sched_destroy(s)
     for H in hams:
         P.prx_ham_destroy(H)
+
+
+def test_rotation_jump_table_is_generated_from_its_script(tmp_path):
+    """csrc/rot_jump_f32m4.inc is the output of csrc/gen_rot_jump.py, and
+    every variant has 32 FMAs and one branch (the fixed stride the computed
+    jump relies on)."""
+    import importlib.util
+    import shutil
+    csrc = os.path.join(ROOT, "paper_2504_17881_amd", "csrc")
+    shutil.copy(os.path.join(csrc, "gen_rot_jump.py"), tmp_path / "gen_rot_jump.py")
+    spec = importlib.util.spec_from_file_location("gen_rot_jump", tmp_path / "gen_rot_jump.py")
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    gen.main()
+    with open(tmp_path / "rot_jump_f32m4.inc") as f, open(os.path.join(csrc, "rot_jump_f32m4.inc")) as g:
+        assert f.read() == g.read()
+    lines = gen.block()
+    start, end = lines.index("2:"), lines.index("3:")
+    body = lines[start + 1:end]
+    assert len(body) == 64 * 33
+    for var in range(64):
+        v = body[33 * var:33 * (var + 1)]
+        assert all(x.startswith("v_fma_f32 ") for x in v[:32]) and v[32] == "s_branch 3f"
+        # each amplitude register is written once (8 disjoint pairs)
+        dst = [x.split()[1].rstrip(",") for x in v[:32]]
+        assert sorted(dst) == sorted(f"%{i}" for i in range(32))
+    assert lines[0] == "s_min_u32 %32, %35, 63" and gen.VARIANT_BYTES == 260
