@@ -312,8 +312,8 @@ typedef struct prx_graph prx_graph;
 /* Plans S independent runs: sample s applies sched[s] to its own state
  * (2^n[s] amplitudes of dtype) and reports <basis_idx[s]|psi_s> (the
  * observable of the qDRIFT and partially randomised estimators, Methods).
- * A sample of at least 13 qubits (complex64; 11 for complex128) is
- * segmented into tile passes of that many tile qubits with up to 9 virtual
+ * A sample of at least 12 qubits (complex64; 11 for complex128) is
+ * segmented into tile passes of that many tile qubits with up to 8 virtual
  * qubits (7 for complex128); a smaller one into span passes of rank 4.  Round p applies pass p
  * of every sample that has one, as one grid-stride kernel over that round's
  * (sample, tile-set) items and one over its (sample, slice) items, so all

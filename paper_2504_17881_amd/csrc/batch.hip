@@ -1,8 +1,8 @@
 // Batched execution of many independent samples (qDRIFT or partially
 // randomised draws, circuits of uneven qubit counts).
 //
-// Samples that hold a tile frame (n >= B: 13 qubits at complex64, 11 at
-// complex128) are planned into tile passes only, with up to 9 virtual
+// Samples that hold a tile frame (n >= B: 12 qubits at complex64, 11 at
+// complex128) are planned into tile passes only, with up to 8 virtual
 // qubits (7 at complex128, every tile keeping 16 contiguous amplitudes): a
 // random-order qDRIFT sequence then fuses 2-2.5 times more rotations per HBM
 // pass than with spans.  Smaller samples are planned into
@@ -27,12 +27,12 @@ namespace prx {
 static constexpr int kBatchRank = 4;
 static constexpr uint64_t kSliceCosets = 8192;
 static constexpr int kBatchTileM = 4;
-static constexpr int kBatchMaxVirtual = 9;
+static constexpr int kBatchMaxVirtual = 8;
 // Tile rounds launch one workgroup per (sample, tile-set) item up to this
 // many (the hardware keeps as many resident as fit and starts the next as
 // soon as one ends), striding beyond it.
 static constexpr uint64_t kTileGridCap = 1u << 20;
-static int batch_tile_qubits(prx_dtype dt) { return dt == PRX_C64 ? 13 : 11; }
+static int batch_tile_qubits(prx_dtype dt) { return dt == PRX_C64 ? 12 : 11; }
 
 struct BSample {
     uint64_t psi;       // device address of the state
@@ -502,7 +502,7 @@ prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
         if (titems) {
             const unsigned grid = (unsigned)std::min<uint64_t>(titems, kTileGridCap);
             if (b->dtype == PRX_C64)
-                hipLaunchKernelGGL((k_batch_tile_round<float, 13, kBatchTileM>), dim3(grid),
+                hipLaunchKernelGGL((k_batch_tile_round<float, 12, kBatchTileM>), dim3(grid),
                                    dim3(tile_threads), 0, st, ta.samples, ta.passes, ta.chunks,
                                    ta.rots, ta.prefixW, ta.order, p, tactive, titems);
             else

@@ -211,7 +211,7 @@ def test_batch_create_host_checks():
         P.prx_ham_destroy(H)
 
 
-@pytest.mark.parametrize("dtype,B", [(P.PRX_C64, 13), (P.PRX_C128, 11)])
+@pytest.mark.parametrize("dtype,B", [(P.PRX_C64, 12), (P.PRX_C128, 11)])
 def test_batch_info_splits_samples_by_tile_frame(dtype, B):
     """Samples of at least B qubits are planned as tile-only plans with the
     batch's fixed options; the rest into span passes."""
@@ -228,7 +228,7 @@ def test_batch_info_splits_samples_by_tile_frame(dtype, B):
     P.prx_batch_destroy(b)
     assert info["samples"] == len(ns)
     assert info["tile_samples"] == sum(n >= B for n in ns)
-    opts = dict(tile_qubits=B, chunk_rank=4, max_fuse=128, max_virtual=9, renorm_every=-1,
+    opts = dict(tile_qubits=B, chunk_rank=4, max_fuse=128, max_virtual=8, renorm_every=-1,
                 tile_only=1)
     tile_passes, tile_sweeps, counts = 0, 0.0, []
     for n, s in zip(ns, scheds):

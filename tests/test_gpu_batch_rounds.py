@@ -67,7 +67,7 @@ def test_rounds_match_oracle_per_sample(dtype):
 
 @pytest.mark.parametrize("dtype", [P.PRX_C64, P.PRX_C128])
 def test_tile_rounds_with_many_virtual_qubits(dtype):
-    """Larger samples (tile passes with up to 9 virtual qubits at complex64, 7
+    """Larger samples (tile passes with up to 8 virtual qubits at complex64, 7
     at complex128) of uneven pass counts next to span samples, checked
     element by element against the oracle."""
     ns = [13, 17, 20, 10, 18, 11]
@@ -77,7 +77,7 @@ def test_tile_rounds_with_many_virtual_qubits(dtype):
     psis = [basis_state(n, b, dtype) for n, b in zip(ns, basis)]
     b = P.prx_batch_create(ns, scheds, dtype, basis)
     info = P.prx_batch_get_info(b)
-    assert info["tile_samples"] == sum(n >= (13 if dtype == P.PRX_C64 else 11) for n in ns)
+    assert info["tile_samples"] == sum(n >= (12 if dtype == P.PRX_C64 else 11) for n in ns)
     ws = workspace(P.prx_batch_workspace_bytes(b))
     ovd = torch.zeros(2 * len(ns), dtype=torch.float64, device=dev())
     P.prx_batch_upload(b, psis, ws)
