@@ -164,6 +164,37 @@ struct TilePersist {
     static constexpr bool value = sizeof(T) == 4 && B >= 13;
 };
 
+// State access of a tile pass.  Workgroups that own one tile-set stream it
+// with non-temporal loads and stores (each amplitude is read and written once
+// per pass; measured 3 % faster with 12-qubit tile-sets); the persistent
+// kernel, whose prefetched loads overlap the previous set's stores, is
+// faster with ordinary ones (non-temporal: 7 % slower).
+template <bool NT, typename T>
+__device__ __forceinline__ Cx<T> tile_load(const Cx<T> *p) {
+    if constexpr (NT) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+        Cx<T> r;
+        r.re = v.x;
+        r.im = v.y;
+        return r;
+    } else {
+        return *p;
+    }
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void tile_store(Cx<T> *p, const Cx<T> &a) {
+    if constexpr (NT) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        v2 v;
+        v.x = a.re;
+        v.y = a.im;
+        __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+    } else {
+        *p = a;
+    }
+}
+
 template <typename T, int B, int M>
 __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, TileArgs a,
                                                       const RotRec<T> *__restrict__ rots,
@@ -226,7 +257,7 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
     if (w < nsets) {
         const uint64_t b0 = base_of(tile_of(w));
 #pragma unroll
-        for (int u = 0; u < PER; ++u) r[u] = psi[b0 ^ a.uoff[u]];
+        for (int u = 0; u < PER; ++u) r[u] = tile_load<!PERSIST>(psi + (b0 ^ a.uoff[u]));
 #pragma unroll
         for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
         __syncthreads();
@@ -239,7 +270,7 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
         if (next) {
             const uint64_t bn = base_of(tile_of(wn));
 #pragma unroll
-            for (int u = 0; u < PER; ++u) r[u] = psi[bn ^ a.uoff[u]];
+            for (int u = 0; u < PER; ++u) r[u] = tile_load<!PERSIST>(psi + (bn ^ a.uoff[u]));
         }
 
         tile_chunks<T, B, M>(lds_raw, tmask, tb, chunks + a.chunk_begin, a.chunk_count, rots);
@@ -254,7 +285,7 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
                 Cx<T> o = q[u];
                 o.re *= s;
                 o.im *= s;
-                psi[base ^ a.uoff[u]] = o;
+                tile_store<!PERSIST>(psi + (base ^ a.uoff[u]), o);
                 part = fma(o.re, o.re, part);
                 part = fma(o.im, o.im, part);
             }
