@@ -296,6 +296,10 @@ prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sche
         tile_cfg.renorm_every = -1;
         tile_cfg.max_fuse = 128;
         tile_cfg.max_virtual = kBatchMaxVirtual;
+        // exact reorders: a later rotation that fits the pass's frame and
+        // commutes with every rotation it passes joins the pass (10-20 %
+        // fewer passes on random-order qDRIFT sequences)
+        tile_cfg.commuting = true;
         for (size_t s = 0; s < S; ++s) {
             const bool tile = n[s] >= TB;
             prx_plan *P = nullptr;

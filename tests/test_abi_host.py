@@ -214,7 +214,8 @@ def test_batch_create_host_checks():
 @pytest.mark.parametrize("dtype,B", [(P.PRX_C64, 12), (P.PRX_C128, 11)])
 def test_batch_info_splits_samples_by_tile_frame(dtype, B):
     """Samples of at least B qubits are planned as tile-only plans with the
-    batch's fixed options; the rest into span passes."""
+    batch's fixed options (exact commuting reorders on); the rest into span
+    passes."""
     ns = [6, 10, 11, 12, 13, 14]
     hams, scheds = [], []
     for i, n in enumerate(ns):
@@ -229,7 +230,7 @@ def test_batch_info_splits_samples_by_tile_frame(dtype, B):
     assert info["samples"] == len(ns)
     assert info["tile_samples"] == sum(n >= B for n in ns)
     opts = dict(tile_qubits=B, chunk_rank=4, max_fuse=128, max_virtual=8, renorm_every=-1,
-                tile_only=1)
+                tile_only=1, commuting=1)
     tile_passes, tile_sweeps, counts = 0, 0.0, []
     for n, s in zip(ns, scheds):
         if n < B:

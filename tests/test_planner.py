@@ -202,27 +202,29 @@ def test_chunk_lanes_hit_distinct_lds_banks(dtype, bank_bits):
     P.prx_ham_destroy(H)
 
 
-@pytest.mark.parametrize("n,dtype,B", [
-    (12, P.PRX_C64, 12), (16, P.PRX_C64, 12), (11, P.PRX_C128, 11), (14, P.PRX_C128, 11),
+@pytest.mark.parametrize("n,dtype,B,commuting", [
+    (12, P.PRX_C64, 12, 1), (16, P.PRX_C64, 12, 1), (16, P.PRX_C64, 12, 0),
+    (11, P.PRX_C128, 11, 1), (14, P.PRX_C128, 11, 1), (14, P.PRX_C128, 11, 0),
 ])
-def test_tile_only_plans_of_batched_samples(n, dtype, B):
+def test_tile_only_plans_of_batched_samples(n, dtype, B, commuting):
     """The form batched samples take: qDRIFT draws in random order, every pass
     a tile pass (B tile qubits, rank-4 chunks, up to 8 virtual qubits while
-    16 contiguous amplitudes remain, no renormalisation), reproducing the
-    oracle through the interpreter."""
+    16 contiguous amplitudes remain, no renormalisation, commuting rotations
+    brought forward when they fit), reproducing the oracle through the
+    interpreter."""
     x, z, h = synth.jw_hamiltonian(n, 80, 1000 + n)
     H = P.prx_ham_create(n, x, z, h)
     s = P.prx_sched_qdrift(H, 1.0, 400, n)
     _, rx, rz, rp = P.prx_sched_view(s)
     opts = dict(tile_qubits=B, chunk_rank=4, max_fuse=128, max_virtual=8, renorm_every=-1,
-                tile_only=1)
+                tile_only=1, commuting=commuting)
     pl = P.prx_plan_create(s, n, dtype, 0, len(rx), P.PRX_FUSED, opts)
     info = P.prx_plan_get_info(pl)
     assert info["tile_passes"] == info["passes"] > 0
     for pi in range(info["passes"]):
         ps = P.prx_plan_pass(pl, pi)
         assert ps["g"] <= min(8, n - B, B - 4) and ps["b"] == B - ps["g"]
-    _check_composition(pl, rx, rz, rp)
+    _check_composition(pl, rx, rz, rp, commuting=bool(commuting))
     _check_closure(pl, n)
     psi0 = synth.gaussian_state(n, 5)
     ref = sv.c_apply_rotations(psi0, rx, rz, rp)
