@@ -314,7 +314,9 @@ typedef struct prx_graph prx_graph;
  * observable of the qDRIFT and partially randomised estimators, Methods).
  * A sample of at least 12 qubits (complex64; 11 for complex128) is
  * segmented into tile passes of that many tile qubits with up to 8 virtual
- * qubits (7 for complex128); a smaller one into span passes of rank 4.  Round p applies pass p
+ * qubits (7 for complex128), bringing a later rotation forward into a pass
+ * when it commutes with every rotation it passes (the product is unchanged;
+ * only the rounding order differs); a smaller one into span passes of rank 4.  Round p applies pass p
  * of every sample that has one, as one grid-stride kernel over that round's
  * (sample, tile-set) items and one over its (sample, slice) items, so all
  * samples share every launch and no workgroup waits on another.  Host only;
