@@ -246,3 +246,24 @@ def test_tile_only_rejects_small_states_and_plain_kernel():
             P.prx_plan_create(s, n, P.PRX_C64, 0, 20, kernel, opts)
         assert e.value.status == P.PRX_ERR_INVALID
     P.prx_sched_destroy(s)
+
+
+def test_random_workload_exercises_every_rank4_variant():
+    """The complex64 random-rotation parity workload (GPU test
+    test_random_rotations_n14_c64) reaches all 64 non-diagonal static-sign
+    variants of rank-4 chunks, i.e. every entry of the kernels' jump table."""
+    import collections
+    w = synth.WORKLOADS["random_n14"]
+    n, M = w["n"], w["M"]
+    x, z, phi = synth.random_pauli_rotations(n, M, seed=w["rot_seed"])
+    s = _sched(n, x, z, phi)
+    pl = P.prx_plan_create(s, n, P.PRX_C64, 0, M, P.PRX_FUSED)
+    info = P.prx_plan_get_info(pl)
+    used = collections.Counter()
+    for i in range(info["kernel_rotations"]):
+        r = P.prx_plan_rotation(pl, i)
+        if r["static_sign"] and r["var"] < 64:
+            used[r["var"]] += 1
+    assert sorted(used) == list(range(64))
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
