@@ -153,6 +153,31 @@ def test_trotter1_n32_c64_tuned_launch_against_c128_plain_prefix():
     P.prx_ham_destroy(H)
 
 
+def test_trotter1_n32_c128_tuned_launch_against_plain():
+    """The committed autotune entry for n = 32 complex128 (12-qubit tile-sets,
+    up to 8 virtual qubits, PRX_AUTO) against the complex128 one-rotation
+    sweep on rotations 2500..2999 of the benchmark schedule (64 GiB each)."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    P.prx_autotune_load(os.path.join(root, "paper_2504_17881_amd", "tuning", "gfx950.json"))
+    H, s = _jw_sched(32, 5000, 0, 1, 0.5, 4, True)
+    k0 = synth.basis_index(32)
+    r0, R = 2500, 500
+    a = basis_state(32, k0, P.PRX_C128)
+    info = apply(a, 32, P.PRX_C128, s, P.PRX_AUTO, r0, r0 + R)
+    assert info["tile_qubits"] == 12 and info["tile_passes"] > 0
+    d_norm = math.sqrt(P.prx_norm2(a, 32, P.PRX_C128, workspace(P.prx_reduce_workspace_bytes(32))))
+    oa = P.prx_amplitude(a, 32, P.PRX_C128, k0)
+    b = basis_state(32, k0, P.PRX_C128)
+    apply(b, 32, P.PRX_C128, s, P.PRX_PLAIN, r0, r0 + R)
+    d = _diff_norm(a, b)
+    ob = P.prx_amplitude(b, 32, P.PRX_C128, k0)
+    print(f"[n32 c128 tuned {R}] passes {info['passes']} err_l2 = {d:.3e}, "
+          f"|d overlap| = {abs(oa - ob):.3e}", flush=True)
+    assert d <= 1e-12 and abs(oa - ob) <= 1e-12 and abs(d_norm - 1.0) <= 1e-12
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
+
+
 def _partial(n):
     x, z, h = synth.jw_hamiltonian(n, 8200, 0)
     H = P.prx_ham_create(n, x, z, h)
