@@ -151,6 +151,8 @@ def test_trotter1_n32_c64_tuned_launch_against_c128_plain_prefix():
     assert d <= 8 * EPS32 * math.sqrt(R) and abs(oa - ob) <= 1e-4
     P.prx_sched_destroy(s)
     P.prx_ham_destroy(H)
+    del a, b
+    torch.cuda.empty_cache()
 
 
 def test_trotter1_n32_c128_tuned_launch_against_plain():
@@ -176,6 +178,8 @@ def test_trotter1_n32_c128_tuned_launch_against_plain():
     assert d <= 1e-12 and abs(oa - ob) <= 1e-12 and abs(d_norm - 1.0) <= 1e-12
     P.prx_sched_destroy(s)
     P.prx_ham_destroy(H)
+    del a, b
+    torch.cuda.empty_cache()
 
 
 def _partial(n):
