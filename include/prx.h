@@ -169,6 +169,8 @@ typedef struct {
     size_t workspace_bytes;   /* bytes prx_plan_execute needs */
     double mean_fuse;         /* rotations per pass */
     int tile_qubits, chunk_rank;
+    int n;                    /* qubits of the state the plan applies to */
+    int dtype;                /* prx_dtype of that state */
 } prx_plan_info;
 
 /* Segments rotations [begin, end) of `sched` for a 2^n state of `dtype`
@@ -220,6 +222,10 @@ typedef struct {
     double scale;
     double fscale[6];                 /* span: pending per-slot factors (see prx_rot_info) */
     int norm_out, renorm_in;          /* C64 renormalisation hand-off */
+    unsigned grid_blocks;             /* workgroups of the pass's launch (an upper bound for
+                                         persistent tile launches, which use the resident
+                                         count); the kernels stride over the rest */
+    unsigned block_threads;           /* threads per workgroup */
 } prx_pass_info;
 
 /* A chunk of a tile pass: basis directions in the workgroup frame; thread t
@@ -373,11 +379,16 @@ void prx_graph_destroy(prx_graph *g);
 /* Autotuning.                                                         */
 /* ------------------------------------------------------------------ */
 
-/* Times candidate (tile_qubits, chunk_rank, max_fuse) settings of the
- * fused planner on `sched` applied to psi (whose contents are destroyed),
- * and records the fastest for (n, dtype) in the in-process cache used by
- * PRX_AUTO.  trials_out (nullable) receives the number of settings timed.
- * Synchronises. */
+/* Times candidate settings of the fused planner on `sched` applied to psi
+ * (whose contents are destroyed), and records the fastest for (n, dtype)
+ * in the in-process cache used by PRX_AUTO.  The search runs in stages:
+ * every built tile shape (tile_qubits, chunk_rank; the shape fixes the
+ * workgroup size 2^(tile_qubits - chunk_rank) and the wave layout of a
+ * tile-set) with the most virtual qubits it allows; the virtual-qubit count
+ * for the two fastest shapes; then max_fuse, span_max and commuting reorders
+ * around the best.  Each setting is timed on one execution after a warm-up
+ * execution.  trials_out (nullable) receives the number of settings timed.
+ * INVALID if no setting's workspace fits ws_bytes.  Synchronises. */
 prx_status prx_autotune(void *psi, int n, prx_dtype dtype, const prx_sched *sched, void *ws,
                         size_t ws_bytes, void *stream, prx_plan_opts *best_out,
                         int *trials_out);

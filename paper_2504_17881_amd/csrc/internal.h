@@ -159,8 +159,13 @@ hipError_t launch_tile(prx_dtype dt, int B, int m, void *psi, const TileArgs &a,
 static constexpr unsigned kRenormStage = 128;
 hipError_t launch_renorm_finish(const double *partials, unsigned count, double *scale_out,
                                 hipStream_t s);
+// Workgroups of one launch: at most kMaxGridBlocks (at 256 threads, 2^30
+// work-items, inside a dispatch's 32-bit work-item range); the kernels
+// stride over the rest.
+static constexpr uint64_t kMaxGridBlocks = 1ull << 22;
 unsigned span_blocks(int n, int m);
 unsigned tile_blocks(int n, int B);
+unsigned plain_blocks(int n, bool diag);
 bool span_supported(prx_dtype dt, int m);
 bool tile_supported(prx_dtype dt, int B, int m);
 

@@ -37,45 +37,51 @@ namespace prx {
 
 // ----------------------------------------------------------------- plain
 
+// Launch grids are capped at kMaxGridBlocks workgroups (2^30 work-items at
+// 256 threads, inside the 32-bit work-item range of a dispatch); the sweep
+// kernels stride over the rest of the state.
 template <typename T, int U>
 __global__ void __launch_bounds__(256) k_plain_pair(Cx<T> *__restrict__ psi, PlainArgs a,
                                                     uint64_t npairs) {
     const T c = (T)a.c;
     const T be = (T)a.beta;
-    const uint64_t base = (uint64_t)blockIdx.x * (256u * U) + threadIdx.x;
-    uint64_t k[U], kp[U];
-    Cx<T> u[U], w[U];
+    const uint64_t stride = (uint64_t)gridDim.x * (256u * U);
+    for (uint64_t base = (uint64_t)blockIdx.x * (256u * U) + threadIdx.x; base < npairs;
+         base += stride) {
+        uint64_t k[U], kp[U];
+        Cx<T> u[U], w[U];
 #pragma unroll
-    for (int i = 0; i < U; ++i) {
-        const uint64_t j = base + (uint64_t)i * 256u;
-        k[i] = insert_zero64(j < npairs ? j : 0, a.pivot);
-        kp[i] = k[i] ^ a.x;
-        if (j < npairs) {
-            u[i] = psi[k[i]];
-            w[i] = psi[kp[i]];
+        for (int i = 0; i < U; ++i) {
+            const uint64_t j = base + (uint64_t)i * 256u;
+            k[i] = insert_zero64(j < npairs ? j : 0, a.pivot);
+            kp[i] = k[i] ^ a.x;
+            if (j < npairs) {
+                u[i] = psi[k[i]];
+                w[i] = psi[kp[i]];
+            }
         }
-    }
 #pragma unroll
-    for (int i = 0; i < U; ++i) {
-        const uint64_t j = base + (uint64_t)i * 256u;
-        if (j >= npairs) continue;
-        const uint32_t sk = parity64(k[i] & a.z);
-        const T bk = flip(be, sk ^ (uint32_t)a.nY_odd);  // beta sigma(k'), used for new[k]
-        const T bkp = flip(be, sk);                      // beta sigma(k),  used for new[k']
-        Cx<T> nu, nw;
-        if (a.beta_imag) {
-            nu.re = c * u[i].re - bk * w[i].im;
-            nu.im = c * u[i].im + bk * w[i].re;
-            nw.re = c * w[i].re - bkp * u[i].im;
-            nw.im = c * w[i].im + bkp * u[i].re;
-        } else {
-            nu.re = c * u[i].re + bk * w[i].re;
-            nu.im = c * u[i].im + bk * w[i].im;
-            nw.re = c * w[i].re + bkp * u[i].re;
-            nw.im = c * w[i].im + bkp * u[i].im;
+        for (int i = 0; i < U; ++i) {
+            const uint64_t j = base + (uint64_t)i * 256u;
+            if (j >= npairs) continue;
+            const uint32_t sk = parity64(k[i] & a.z);
+            const T bk = flip(be, sk ^ (uint32_t)a.nY_odd);  // beta sigma(k'), used for new[k]
+            const T bkp = flip(be, sk);                      // beta sigma(k),  used for new[k']
+            Cx<T> nu, nw;
+            if (a.beta_imag) {
+                nu.re = c * u[i].re - bk * w[i].im;
+                nu.im = c * u[i].im + bk * w[i].re;
+                nw.re = c * w[i].re - bkp * u[i].im;
+                nw.im = c * w[i].im + bkp * u[i].re;
+            } else {
+                nu.re = c * u[i].re + bk * w[i].re;
+                nu.im = c * u[i].im + bk * w[i].im;
+                nw.re = c * w[i].re + bkp * u[i].re;
+                nw.im = c * w[i].im + bkp * u[i].im;
+            }
+            psi[k[i]] = nu;
+            psi[kp[i]] = nw;
         }
-        psi[k[i]] = nu;
-        psi[kp[i]] = nw;
     }
 }
 
@@ -84,22 +90,25 @@ __global__ void __launch_bounds__(256) k_plain_diag(Cx<T> *__restrict__ psi, Pla
                                                     uint64_t N) {
     const T c = (T)a.c;
     const T s = (T)a.beta;  // beta = i sin(phi) for x = 0
-    const uint64_t base = (uint64_t)blockIdx.x * (256u * U) + threadIdx.x;
-    Cx<T> u[U];
+    const uint64_t stride = (uint64_t)gridDim.x * (256u * U);
+    for (uint64_t base = (uint64_t)blockIdx.x * (256u * U) + threadIdx.x; base < N;
+         base += stride) {
+        Cx<T> u[U];
 #pragma unroll
-    for (int i = 0; i < U; ++i) {
-        const uint64_t k = base + (uint64_t)i * 256u;
-        if (k < N) u[i] = psi[k];
-    }
+        for (int i = 0; i < U; ++i) {
+            const uint64_t k = base + (uint64_t)i * 256u;
+            if (k < N) u[i] = psi[k];
+        }
 #pragma unroll
-    for (int i = 0; i < U; ++i) {
-        const uint64_t k = base + (uint64_t)i * 256u;
-        if (k >= N) continue;
-        const T bs = flip(s, parity64(k & a.z));
-        Cx<T> nu;
-        nu.re = c * u[i].re - bs * u[i].im;
-        nu.im = c * u[i].im + bs * u[i].re;
-        psi[k] = nu;
+        for (int i = 0; i < U; ++i) {
+            const uint64_t k = base + (uint64_t)i * 256u;
+            if (k >= N) continue;
+            const T bs = flip(s, parity64(k & a.z));
+            Cx<T> nu;
+            nu.re = c * u[i].re - bs * u[i].im;
+            nu.im = c * u[i].im + bs * u[i].re;
+            psi[k] = nu;
+        }
     }
 }
 
@@ -112,39 +121,44 @@ __global__ void __launch_bounds__(256) k_span(Cx<T> *__restrict__ psi, SpanArgs 
                                               double *__restrict__ norm_out) {
     __shared__ double red[4];
     const uint64_t ncos = 1ull << (a.n - M);
-    const uint64_t t = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-    const bool live = t < ncos;
-    uint64_t k0 = live ? t : 0;
-#pragma unroll
-    for (int i = 0; i < M; ++i) k0 = insert_zero64(k0, a.pivot[i]);
     uint64_t X[1 << M];
     X[0] = 0;
 #pragma unroll
     for (int v = 1; v < (1 << M); ++v) X[v] = X[v & (v - 1)] ^ a.basis[__builtin_ctz(v)];
-    Cx<T> amp[1 << M];
-    if (live) {
-#pragma unroll
-        for (int v = 0; v < (1 << M); ++v) amp[v] = psi[k0 ^ X[v]];
-    }
-    apply_rots<T, M>(amp, k0, 0, rots + a.rot_begin, a.rot_count);
     double sc = a.scale;
     if (renorm_in) sc *= *renorm_in;
     double F[1 << M];
     pending_factors<M>(F, a.fscale);
     double nrm = 0.0;
-    if (live) {
-        T part = 0;  // the thread's 2^M squares in the state's precision
+    // grid-stride over the cosets; every thread of a block runs the same
+    // number of iterations (the rotation loop's control stays uniform)
+    const uint64_t stride = (uint64_t)gridDim.x * 256u;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * 256u; t0 < ncos; t0 += stride) {
+        const uint64_t t = t0 + threadIdx.x;
+        const bool live = t < ncos;
+        uint64_t k0 = live ? t : 0;
 #pragma unroll
-        for (int v = 0; v < (1 << M); ++v) {
-            const T s = (T)(sc * F[v]);
-            Cx<T> o;
-            o.re = amp[v].re * s;
-            o.im = amp[v].im * s;
-            psi[k0 ^ X[v]] = o;
-            part = fma(o.re, o.re, part);
-            part = fma(o.im, o.im, part);
+        for (int i = 0; i < M; ++i) k0 = insert_zero64(k0, a.pivot[i]);
+        Cx<T> amp[1 << M];
+        if (live) {
+#pragma unroll
+            for (int v = 0; v < (1 << M); ++v) amp[v] = psi[k0 ^ X[v]];
         }
-        nrm = (double)part;
+        apply_rots<T, M>(amp, k0, 0, rots + a.rot_begin, a.rot_count);
+        if (live) {
+            T part = 0;  // the thread's 2^M squares in the state's precision
+#pragma unroll
+            for (int v = 0; v < (1 << M); ++v) {
+                const T s = (T)(sc * F[v]);
+                Cx<T> o;
+                o.re = amp[v].re * s;
+                o.im = amp[v].im * s;
+                psi[k0 ^ X[v]] = o;
+                part = fma(o.re, o.re, part);
+                part = fma(o.im, o.im, part);
+            }
+            nrm += (double)part;
+        }
     }
     if (norm_out) {
         nrm = block_sum<256>(nrm, red);
@@ -244,7 +258,8 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
 
     // Set order: persistent workgroups stride over the sets; otherwise the
     // workgroups, dispatched round-robin over the 8 XCDs, give each XCD a
-    // contiguous range of sets.
+    // contiguous range of sets (and stride over the rest when the grid is
+    // capped: the set count is then a multiple of the grid).
     uint32_t w = blockIdx.x;
     if (!PERSIST && (gridDim.x & 7u) == 0u)
         w = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
@@ -263,7 +278,7 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
         for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
         __syncthreads();
     }
-    for (; w < nsets; w += PERSIST ? gridDim.x : nsets) {
+    for (; w < nsets; w += gridDim.x) {
         const uint64_t tb = tile_of(w);
         const uint64_t base = base_of(tb);
         const uint32_t wn = w + gridDim.x;
@@ -434,17 +449,22 @@ __global__ void __launch_bounds__(256) k_scale(Cx<T> *__restrict__ a, uint64_t N
 // ------------------------------------------------------------- launchers
 
 static unsigned ceil_div_u(uint64_t a, uint64_t b) { return (unsigned)((a + b - 1) / b); }
+static unsigned capped_blocks(uint64_t want) {
+    return (unsigned)std::min<uint64_t>(want ? want : 1, kMaxGridBlocks);
+}
 
 template <typename T>
 static hipError_t plain_t(void *psi, const PlainArgs &a, hipStream_t s) {
     constexpr int U = 4;
     if (a.x == 0) {
         const uint64_t N = 1ull << a.n;
-        hipLaunchKernelGGL((k_plain_diag<T, U>), dim3(ceil_div_u(N, 256u * U)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_plain_diag<T, U>), dim3(capped_blocks((N + 256u * U - 1) / (256u * U))),
+                           dim3(256), 0, s,
                            (Cx<T> *)psi, a, N);
     } else {
         const uint64_t np = 1ull << (a.n - 1);
-        hipLaunchKernelGGL((k_plain_pair<T, U>), dim3(ceil_div_u(np, 256u * U)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_plain_pair<T, U>), dim3(capped_blocks((np + 256u * U - 1) / (256u * U))),
+                           dim3(256), 0, s,
                            (Cx<T> *)psi, a, np);
     }
     return hipGetLastError();
@@ -454,8 +474,12 @@ hipError_t launch_plain(prx_dtype dt, void *psi, const PlainArgs &a, hipStream_t
     return dt == PRX_C64 ? plain_t<float>(psi, a, s) : plain_t<double>(psi, a, s);
 }
 
-unsigned span_blocks(int n, int m) { return ceil_div_u(1ull << (n - m), 256u); }
-unsigned tile_blocks(int n, int B) { return (unsigned)(1ull << (n - B)); }
+unsigned span_blocks(int n, int m) { return capped_blocks(((1ull << (n - m)) + 255u) / 256u); }
+unsigned tile_blocks(int n, int B) { return capped_blocks(1ull << (n - B)); }
+unsigned plain_blocks(int n, bool diag) {
+    const uint64_t items = diag ? (1ull << n) : (1ull << (n - 1));
+    return capped_blocks((items + 1023u) / 1024u);
+}
 
 // Persistent tile kernels stride over the 2^(n-B) tile-sets with the
 // workgroups that fit on the device at once (cached per device and kernel).

@@ -791,6 +791,8 @@ prx_status prx_plan_get_info(const prx_plan *P, prx_plan_info *o) {
     o->mean_fuse = P->passes.empty() ? 0.0 : (double)P->rots.size() / (double)P->passes.size();
     o->tile_qubits = P->cfg.B;
     o->chunk_rank = P->cfg.m;
+    o->n = P->n;
+    o->dtype = (int)P->dtype;
     return PRX_OK;
 }
 
@@ -933,6 +935,16 @@ prx_status prx_plan_pass(const prx_plan *P, size_t i, prx_pass_info *o) {
     for (int k = 0; k < kMaxChunkRank; ++k) o->fscale[k] = ps.fscale[k];
     o->norm_out = ps.norm_out;
     o->renorm_in = ps.renorm_in;
+    if (ps.kind == kPlain) {
+        o->grid_blocks = plain_blocks(P->n, P->rots[ps.r0].x == 0);
+        o->block_threads = 256;
+    } else if (ps.kind == kSpan) {
+        o->grid_blocks = span_blocks(P->n, ps.m);
+        o->block_threads = 256;
+    } else {
+        o->grid_blocks = tile_blocks(P->n, ps.B);
+        o->block_threads = 1u << (ps.B - ps.m);
+    }
     return PRX_OK;
 }
 

@@ -3,6 +3,7 @@
 // the caller's schedule and state with HIP events, keeps the fastest per
 // (arch, n, dtype) in an in-process cache that PRX_AUTO plans read, and
 // saves/loads that cache as JSON.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -91,36 +92,21 @@ prx_status prx_autotune_progress(void *psi, int n, prx_dtype dtype, const prx_sc
     hipStream_t s = (hipStream_t)stream;
     struct Shape { int B, m; };
     const Shape shapes[] = {{10, 3}, {10, 4}, {11, 4}, {12, 4}, {12, 5}, {13, 4}, {13, 5}, {14, 4}};
-    std::vector<prx_plan_opts> cands;
-    for (const Shape &sh : shapes) {
-        if (!tile_supported(dtype, sh.B, sh.m) || n < sh.B + 1) continue;
-        for (int g : {1, 2, 3, 5, 8, 10}) {
-            if (sh.B - g < kMinTileLow) continue;
-            for (int f : {64, 128}) {
-                prx_plan_opts o;
-                std::memset(&o, 0, sizeof(o));
-                o.tile_qubits = sh.B;
-                o.chunk_rank = sh.m;
-                o.max_virtual = g;
-                o.max_fuse = f;
-                o.span_max = 4;
-                cands.push_back(o);
-            }
-        }
-    }
-    if (cands.empty()) {  // too small for tiles: span rank only
-        for (int r : {2, 3, 4, 5}) {
-            prx_plan_opts o;
-            std::memset(&o, 0, sizeof(o));
-            o.span_max = r;
-            cands.push_back(o);
-        }
-    }
     float best_ms = 0.f;
     prx_plan_opts best;
     std::memset(&best, 0, sizeof(best));
     int trials = 0;
+    struct Timed {
+        prx_plan_opts o;
+        float ms;
+    };
+    std::vector<Timed> timed;
+    auto same = [](const prx_plan_opts &a, const prx_plan_opts &b) {
+        return std::memcmp(&a, &b, sizeof(a)) == 0;
+    };
     auto run = [&](const prx_plan_opts &o) -> prx_status {
+        for (const Timed &t : timed)
+            if (same(t.o, o)) return PRX_OK;  // already timed
         prx_plan *P = nullptr;
         prx_status st = prx_plan_create(sched, n, dtype, 0, sched->x.size(), PRX_FUSED, &o, &P);
         if (st != PRX_OK) return PRX_OK;  // setting not applicable: skip
@@ -130,6 +116,7 @@ prx_status prx_autotune_progress(void *psi, int n, prx_dtype dtype, const prx_sc
             if (st == PRX_OK) {
                 if (progress) progress(&o, ms, user);
                 ++trials;
+                timed.push_back(Timed{o, ms});
                 if (trials == 1 || ms < best_ms) {
                     best_ms = ms;
                     best = o;
@@ -139,20 +126,63 @@ prx_status prx_autotune_progress(void *psi, int n, prx_dtype dtype, const prx_sc
         prx_plan_destroy(P);
         return st;
     };
-    for (const prx_plan_opts &o : cands) {
-        prx_status st = run(o);
-        if (st != PRX_OK) return st;
+#define PRX_TUNE_RUN(o)                     \
+    do {                                    \
+        prx_status st_ = run(o);            \
+        if (st_ != PRX_OK) return st_;      \
+    } while (0)
+    // Stage 1: every built tile shape (tile qubits B, chunk rank m) with the
+    // most virtual qubits it allows.
+    std::vector<Shape> shapes_ok;
+    for (const Shape &sh : shapes) {
+        if (!tile_supported(dtype, sh.B, sh.m) || n < sh.B + 1) continue;
+        shapes_ok.push_back(sh);
+        prx_plan_opts o;
+        std::memset(&o, 0, sizeof(o));
+        o.tile_qubits = sh.B;
+        o.chunk_rank = sh.m;
+        o.max_virtual = std::min(kMaxVirtual, sh.B - kMinTileLow);
+        o.max_fuse = 128;
+        o.span_max = 4;
+        PRX_TUNE_RUN(o);
     }
-    // second stage: span rank around the best tile setting
-    if (trials > 0) {
-        const prx_plan_opts base = best;
-        for (int r : {3, 5}) {
-            prx_plan_opts o = base;
+    if (shapes_ok.empty()) {  // too small for tiles: span rank only
+        for (int r : {2, 3, 4, 5}) {
+            prx_plan_opts o;
+            std::memset(&o, 0, sizeof(o));
             o.span_max = r;
-            prx_status st = run(o);
-            if (st != PRX_OK) return st;
+            PRX_TUNE_RUN(o);
+        }
+    } else if (trials > 0) {
+        // Stage 2: virtual-qubit count for the two fastest shapes.
+        std::vector<Timed> st1 = timed;
+        std::sort(st1.begin(), st1.end(), [](const Timed &a, const Timed &b) { return a.ms < b.ms; });
+        for (size_t k = 0; k < st1.size() && k < 2; ++k)
+            for (int g : {1, 2, 3, 5, 8, 10}) {
+                prx_plan_opts o = st1[k].o;
+                if (o.tile_qubits - g < kMinTileLow) continue;
+                o.max_virtual = g;
+                PRX_TUNE_RUN(o);
+            }
+        // Stage 3: fusion depth, span rank and commuting reorders around the best.
+        const prx_plan_opts base = best;
+        for (int f : {64, 256}) {
+            prx_plan_opts o = base;
+            o.max_fuse = f;
+            PRX_TUNE_RUN(o);
+        }
+        for (int r : {3, 5}) {
+            prx_plan_opts o = best;
+            o.span_max = r;
+            PRX_TUNE_RUN(o);
+        }
+        {
+            prx_plan_opts o = best;
+            o.commuting = 1;
+            PRX_TUNE_RUN(o);
         }
     }
+#undef PRX_TUNE_RUN
     if (trials == 0) return fail(PRX_ERR_INVALID, "workspace too small for every candidate");
     tune_store(n, dtype, best);
     if (best_out) *best_out = best;

@@ -6,6 +6,12 @@ as integer addresses; streams as ``torch.cuda.Stream`` objects, raw
 integers, or None (the default stream).  A non-OK status raises
 ``PrxError`` carrying the library's message.
 
+A state given as a tensor is checked before its address crosses the ABI:
+it must be a contiguous GPU tensor of 2^n elements whose dtype matches the
+prx dtype (complex64 for PRX_C64, complex128 for PRX_C128); workspaces must
+be contiguous GPU tensors.  Violations raise TypeError or ValueError.
+Integer addresses are passed as given.
+
 The library must have been built (``python -m paper_2504_17881_amd.build``);
 importing this module without it raises immediately.
 """
@@ -65,7 +71,8 @@ class prx_plan_info(ctypes.Structure):
     _fields_ = [("rotations", _sz), ("kernel_rotations", _sz), ("passes", _sz),
                 ("plain_passes", _sz), ("span_passes", _sz), ("tile_passes", _sz),
                 ("workspace_bytes", _sz), ("mean_fuse", ctypes.c_double),
-                ("tile_qubits", ctypes.c_int), ("chunk_rank", ctypes.c_int)]
+                ("tile_qubits", ctypes.c_int), ("chunk_rank", ctypes.c_int),
+                ("n", ctypes.c_int), ("dtype", ctypes.c_int)]
 
 
 class prx_pass_info(ctypes.Structure):
@@ -76,7 +83,8 @@ class prx_pass_info(ctypes.Structure):
                 ("basis", ctypes.c_uint64 * 6), ("pivot", ctypes.c_uint32 * 6),
                 ("vmask", ctypes.c_uint64 * 10), ("tpivot", ctypes.c_uint32 * 10),
                 ("scale", ctypes.c_double), ("fscale", ctypes.c_double * 6),
-                ("norm_out", ctypes.c_int), ("renorm_in", ctypes.c_int)]
+                ("norm_out", ctypes.c_int), ("renorm_in", ctypes.c_int),
+                ("grid_blocks", ctypes.c_uint), ("block_threads", ctypes.c_uint)]
 
 
 class prx_chunk_info(ctypes.Structure):
@@ -175,6 +183,49 @@ def _ptr(buf) -> int | None:
     if isinstance(buf, np.ndarray):
         return buf.ctypes.data
     raise TypeError(f"cannot take the address of {type(buf)!r}")
+
+
+_TORCH_DTYPE_NAME = {PRX_C64: "complex64", PRX_C128: "complex128"}
+
+
+def _is_tensor(buf) -> bool:
+    return torch is not None and isinstance(buf, torch.Tensor)
+
+
+def _state(buf, n: int, dtype: int, what: str = "state") -> int:
+    """Address of a state buffer after checking a torch tensor against the
+    C ABI's contract: a contiguous GPU tensor of 2^n elements whose dtype is
+    the prx dtype's.  Integer addresses pass unchecked (the caller vouches
+    for them)."""
+    if _is_tensor(buf):
+        want = _TORCH_DTYPE_NAME.get(int(dtype))
+        if want is None:
+            raise ValueError(f"{what}: unknown prx dtype {dtype!r}")
+        if buf.dtype != getattr(torch, want):
+            raise TypeError(f"{what}: tensor dtype {buf.dtype} does not match {want}")
+        if not 0 <= int(n) < 64 or buf.numel() != (1 << int(n)):
+            raise ValueError(f"{what}: {buf.numel()} elements, expected 2^{n}")
+        if not buf.is_contiguous():
+            raise ValueError(f"{what}: tensor is not contiguous")
+        if not buf.is_cuda:
+            raise ValueError(f"{what}: tensor is not on a GPU")
+        return buf.data_ptr()
+    if isinstance(buf, int):
+        return buf
+    raise TypeError(f"{what}: expected a torch tensor or a device address, got {type(buf)!r}")
+
+
+def _device_buf(buf, what: str = "workspace") -> int:
+    """Address of a device workspace: a contiguous GPU tensor or an int."""
+    if _is_tensor(buf):
+        if not buf.is_contiguous():
+            raise ValueError(f"{what}: tensor is not contiguous")
+        if not buf.is_cuda:
+            raise ValueError(f"{what}: tensor is not on a GPU")
+        return buf.data_ptr()
+    if isinstance(buf, int):
+        return buf
+    raise TypeError(f"{what}: expected a torch tensor or a device address, got {type(buf)!r}")
 
 
 def _nbytes(buf, given=None) -> int:
@@ -322,12 +373,17 @@ def prx_plan_destroy(plan: int) -> None:
 
 
 def prx_plan_upload(plan: int, ws, stream=None, ws_bytes=None) -> None:
-    _check(_lib.prx_plan_upload(plan, _ptr(ws), _nbytes(ws, ws_bytes), _stream(stream)))
+    _check(_lib.prx_plan_upload(plan, _device_buf(ws), _nbytes(ws, ws_bytes), _stream(stream)))
+
+
+def _plan_state(plan: int, psi) -> int:
+    i = prx_plan_get_info(plan)
+    return _state(psi, i["n"], i["dtype"])
 
 
 def prx_plan_execute(plan: int, psi, ws, stream=None, ws_bytes=None) -> None:
-    _check(_lib.prx_plan_execute(plan, _ptr(psi), _ptr(ws), _nbytes(ws, ws_bytes),
-                                 _stream(stream)))
+    _check(_lib.prx_plan_execute(plan, _plan_state(plan, psi), _device_buf(ws),
+                                 _nbytes(ws, ws_bytes), _stream(stream)))
 
 
 def prx_plan_execute_timed(plan: int, psi, ws, stream=None, ws_bytes=None):
@@ -336,7 +392,8 @@ def prx_plan_execute_timed(plan: int, psi, ws, stream=None, ws_bytes=None):
     pm = np.zeros(max(npass, 1), dtype=np.float32)
     rm = np.zeros(max(npass, 1), dtype=np.float32)
     fp = ctypes.POINTER(ctypes.c_float)
-    _check(_lib.prx_plan_execute_timed(plan, _ptr(psi), _ptr(ws), _nbytes(ws, ws_bytes),
+    _check(_lib.prx_plan_execute_timed(plan, _plan_state(plan, psi), _device_buf(ws),
+                                       _nbytes(ws, ws_bytes),
                                        _stream(stream), pm.ctypes.data_as(fp),
                                        rm.ctypes.data_as(fp)))
     return pm[:npass], rm[:npass]
@@ -375,8 +432,8 @@ def prx_workspace_bytes(n: int, dtype: int, sched: int, kernel: int) -> int:
 
 def prx_apply_range(psi, n: int, dtype: int, sched: int, begin: int, end: int, kernel: int,
                     ws, stream=None, ws_bytes=None) -> None:
-    _check(_lib.prx_apply_range(_ptr(psi), n, dtype, sched, begin, end, kernel, _ptr(ws),
-                                _nbytes(ws, ws_bytes), _stream(stream)))
+    _check(_lib.prx_apply_range(_state(psi, n, dtype), n, dtype, sched, begin, end, kernel,
+                                _device_buf(ws), _nbytes(ws, ws_bytes), _stream(stream)))
 
 
 def prx_reduce_workspace_bytes(n: int) -> int:
@@ -385,35 +442,30 @@ def prx_reduce_workspace_bytes(n: int) -> int:
 
 def prx_overlap(psi0, psi, n: int, dtype: int, ws, stream=None, ws_bytes=None) -> complex:
     out = (ctypes.c_double * 2)()
-    _check(_lib.prx_overlap(_ptr(psi0), _ptr(psi), n, dtype, out, _ptr(ws),
-                            _nbytes(ws, ws_bytes), _stream(stream)))
+    _check(_lib.prx_overlap(_state(psi0, n, dtype, "psi0"), _state(psi, n, dtype), n, dtype,
+                            out, _device_buf(ws), _nbytes(ws, ws_bytes), _stream(stream)))
     return complex(out[0], out[1])
 
 
 def prx_amplitude(psi, n: int, dtype: int, k: int, stream=None) -> complex:
     out = (ctypes.c_double * 2)()
-    _check(_lib.prx_amplitude(_ptr(psi), n, dtype, k, out, _stream(stream)))
+    _check(_lib.prx_amplitude(_state(psi, n, dtype), n, dtype, k, out, _stream(stream)))
     return complex(out[0], out[1])
 
 
 def prx_norm2(psi, n: int, dtype: int, ws, stream=None, ws_bytes=None) -> float:
     v = ctypes.c_double()
-    _check(_lib.prx_norm2(_ptr(psi), n, dtype, ctypes.byref(v), _ptr(ws),
+    _check(_lib.prx_norm2(_state(psi, n, dtype), n, dtype, ctypes.byref(v), _device_buf(ws),
                           _nbytes(ws, ws_bytes), _stream(stream)))
     return v.value
 
 
 def prx_renormalize(psi, n: int, dtype: int, ws, stream=None, ws_bytes=None) -> None:
-    _check(_lib.prx_renormalize(_ptr(psi), n, dtype, _ptr(ws), _nbytes(ws, ws_bytes),
-                                _stream(stream)))
+    _check(_lib.prx_renormalize(_state(psi, n, dtype), n, dtype, _device_buf(ws),
+                                _nbytes(ws, ws_bytes), _stream(stream)))
 
 
 # ------------------------------------------------------------------ batches
-
-def _ptr_array(items):
-    arr = (_vp * len(items))(*[_ptr(p) for p in items])
-    return arr
-
 
 def prx_batch_create(n_list, scheds, dtype: int, basis_idx) -> int:
     S = len(n_list)
@@ -422,7 +474,20 @@ def prx_batch_create(n_list, scheds, dtype: int, basis_idx) -> int:
     ba, bp = _u64(basis_idx)
     out = _vp()
     _check(_lib.prx_batch_create(S, na, sa, dtype, bp, ctypes.byref(out)))
+    _BATCH_SHAPES[out.value] = ([int(v) for v in n_list], int(dtype))
     return out.value
+
+
+# (qubit counts, dtype) of the live batch handles, for checking the states
+# handed to prx_batch_upload
+_BATCH_SHAPES: dict = {}
+
+
+def _batch_states(psis, n_list, dtype) -> list:
+    if len(psis) != len(n_list):
+        raise ValueError(f"{len(psis)} states for {len(n_list)} samples")
+    return [_state(p, n, dtype, f"state of sample {i}")
+            for i, (p, n) in enumerate(zip(psis, n_list))]
 
 
 def prx_batch_workspace_bytes(batch: int) -> int:
@@ -441,47 +506,53 @@ def prx_batch_get_info(batch: int) -> dict:
 
 
 def prx_batch_upload(batch: int, psis, ws, stream=None, ws_bytes=None) -> None:
-    pa = _ptr_array(psis)
-    _check(_lib.prx_batch_upload(batch, pa, _ptr(ws), _nbytes(ws, ws_bytes), _stream(stream)))
+    shape = _BATCH_SHAPES.get(batch)
+    addrs = _batch_states(psis, *shape) if shape else [_device_buf(p, "state") for p in psis]
+    pa = (_vp * len(addrs))(*addrs)
+    _check(_lib.prx_batch_upload(batch, pa, _device_buf(ws), _nbytes(ws, ws_bytes),
+                                 _stream(stream)))
 
 
 def prx_batch_execute(batch: int, ws, overlaps_dev, stream=None, ws_bytes=None) -> None:
-    _check(_lib.prx_batch_execute(batch, _ptr(ws), _nbytes(ws, ws_bytes), _ptr(overlaps_dev),
+    _check(_lib.prx_batch_execute(batch, _device_buf(ws), _nbytes(ws, ws_bytes),
+                                  _device_buf(overlaps_dev, "overlaps"),
                                   _stream(stream)))
 
 
 def prx_batch_check(batch: int, ws, stream=None) -> None:
-    _check(_lib.prx_batch_check(batch, _ptr(ws), _stream(stream)))
+    _check(_lib.prx_batch_check(batch, _device_buf(ws), _stream(stream)))
 
 
 def prx_batch_destroy(batch: int) -> None:
+    _BATCH_SHAPES.pop(batch, None)
     _lib.prx_batch_destroy(batch)
 
 
 def prx_batch_run(psis, n_list, scheds, dtype: int, basis_idx, ws, stream=None,
                   ws_bytes=None) -> np.ndarray:
     S = len(psis)
-    pa = _ptr_array(psis)
+    pa = (_vp * S)(*_batch_states(psis, n_list, dtype))
     na = (ctypes.c_int * S)(*[int(v) for v in n_list])
     sa = (_vp * S)(*scheds)
     ba, bp = _u64(basis_idx)
     out = np.zeros(2 * S, dtype=np.float64)
-    _check(_lib.prx_batch_run(S, pa, na, sa, dtype, bp, out.ctypes.data_as(_dp), _ptr(ws),
-                              _nbytes(ws, ws_bytes), _stream(stream)))
+    _check(_lib.prx_batch_run(S, pa, na, sa, dtype, bp, out.ctypes.data_as(_dp),
+                              _device_buf(ws), _nbytes(ws, ws_bytes), _stream(stream)))
     return out[0::2] + 1j * out[1::2]
 
 
 def prx_batch_graph(batch: int, ws, overlaps_dev, stream, ws_bytes=None) -> int:
     out = _vp()
-    _check(_lib.prx_batch_graph(batch, _ptr(ws), _nbytes(ws, ws_bytes), _ptr(overlaps_dev),
+    _check(_lib.prx_batch_graph(batch, _device_buf(ws), _nbytes(ws, ws_bytes),
+                                _device_buf(overlaps_dev, "overlaps"),
                                 _stream(stream), ctypes.byref(out)))
     return out.value
 
 
 def prx_plan_graph(plan: int, psi, ws, stream, ws_bytes=None) -> int:
     out = _vp()
-    _check(_lib.prx_plan_graph(plan, _ptr(psi), _ptr(ws), _nbytes(ws, ws_bytes), _stream(stream),
-                               ctypes.byref(out)))
+    _check(_lib.prx_plan_graph(plan, _plan_state(plan, psi), _device_buf(ws),
+                               _nbytes(ws, ws_bytes), _stream(stream), ctypes.byref(out)))
     return out.value
 
 
@@ -501,13 +572,15 @@ def prx_autotune(psi, n: int, dtype: int, sched: int, ws, stream=None, ws_bytes=
     best = prx_plan_opts()
     trials = ctypes.c_int()
     if progress is None:
-        _check(_lib.prx_autotune(_ptr(psi), n, dtype, sched, _ptr(ws), _nbytes(ws, ws_bytes),
-                                 _stream(stream), ctypes.byref(best), ctypes.byref(trials)))
+        _check(_lib.prx_autotune(_state(psi, n, dtype), n, dtype, sched, _device_buf(ws),
+                                 _nbytes(ws, ws_bytes), _stream(stream), ctypes.byref(best),
+                                 ctypes.byref(trials)))
     else:
         def _cb(o, ms, _user):
             progress({f: getattr(o.contents, f) for f, _ in prx_plan_opts._fields_}, float(ms))
         cb = _TUNE_PROGRESS(_cb)
-        _check(_lib.prx_autotune_progress(_ptr(psi), n, dtype, sched, _ptr(ws),
+        _check(_lib.prx_autotune_progress(_state(psi, n, dtype), n, dtype, sched,
+                                          _device_buf(ws),
                                           _nbytes(ws, ws_bytes), _stream(stream),
                                           ctypes.byref(best), ctypes.byref(trials), cb, None))
     return {f: getattr(best, f) for f, _ in prx_plan_opts._fields_}, trials.value

@@ -280,3 +280,155 @@ def test_rotation_jump_table_is_generated_from_its_script(tmp_path):
         dst = [x.split()[1].rstrip(",") for x in v[:32]]
         assert sorted(dst) == sorted(f"%{i}" for i in range(32))
     assert lines[0] == "s_min_u32 %32, %35, 63" and gen.VARIANT_BYTES == 260
+
+
+def _code_object(tmp_path, obj_name):
+    """The gfx950 code object of one built translation unit, extracted from
+    its offload bundle (objects built in this tree)."""
+    import subprocess
+    build = os.path.join(ROOT, "paper_2504_17881_amd", "_build")
+    obj = os.path.join(build, obj_name)
+    src = os.path.join(ROOT, "paper_2504_17881_amd", "csrc", obj_name[:-2])
+    if not os.path.exists(obj) or os.path.getmtime(obj) < os.path.getmtime(src):
+        from paper_2504_17881_amd import build as pb
+        pb.build()
+    llvm = "/opt/rocm/llvm/bin"
+    fat = tmp_path / (obj_name + ".fatbin")
+    co = tmp_path / (obj_name + ".co")
+    subprocess.run([f"{llvm}/llvm-objcopy", f"--dump-section=.hip_fatbin={fat}", obj,
+                    str(tmp_path / "scratch.o")], check=True)
+    subprocess.run([f"{llvm}/clang-offload-bundler", "--unbundle", "--type=o",
+                    f"--input={fat}", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
+                    f"--output={co}"], check=True)
+    out = subprocess.run([f"{llvm}/llvm-objdump", "-d", "--no-show-raw-insn", str(co)],
+                         check=True, capture_output=True, text=True).stdout
+    ins = []
+    for line in out.splitlines():
+        m = re.match(r"\s+(\S.*?)\s*//\s*([0-9A-Fa-f]+):", line)
+        if m:
+            ins.append((int(m.group(2), 16), m.group(1).split()[0], m.group(1)))
+    return ins
+
+
+@pytest.mark.parametrize("obj_name", ["kernels.hip.o", "batch.hip.o"])
+def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
+    """Every instance of the computed jump in the built gfx950 code: the
+    table starts right after s_setpc_b64, variant v occupies bytes
+    [260 v, 260 (v + 1)) of it as 32 eight-byte v_fma_f32 and one s_branch
+    to the table's end, and the jump adds (table - return address) and
+    260 * min(var, 63) to the return address.  A different encoding size
+    would send the jump into the middle of an instruction."""
+    ins = _code_object(tmp_path, obj_name)
+    addr = [a for a, _, _ in ins]
+    at = {a: i for i, a in enumerate(addr)}
+    tables = [i for i, (_, op, txt) in enumerate(ins) if op == "s_setpc_b64" and "s[90:91]" in txt]
+    assert tables, "no jump table in the code object"
+    for i in tables:
+        # preamble: s_min_u32, s_mul_i32 260, s_getpc_b64, s_add/addc (var),
+        # s_add/addc (label offset), s_setpc_b64
+        pre = [op for _, op, _ in ins[i - 7:i + 1]]
+        assert pre == ["s_min_u32", "s_mul_i32", "s_getpc_b64", "s_add_u32", "s_addc_u32",
+                       "s_add_u32", "s_addc_u32", "s_setpc_b64"], pre
+        assert ins[i - 7][2].endswith(", 63") and ins[i - 6][2].endswith(", 0x104")
+        ret = addr[i - 4]                       # s_getpc_b64 yields the next address
+        start = addr[i + 1]
+        off = int(ins[i - 2][2].rsplit(",", 1)[1].strip(), 0)
+        assert ret + off == start, (hex(ret), off, hex(start))
+        end = start + 64 * 260
+        for var in range(64):
+            base = start + 260 * var
+            for k in range(32):
+                j = at[base + 8 * k]
+                assert ins[j][1] == "v_fma_f32", (var, k, ins[j])
+            j = at[base + 256]
+            assert ins[j][1] == "s_branch", (var, ins[j])
+            assert addr[j + 1] == base + 260
+        # every branch of the table lands on the table's end
+        for var in range(64):
+            j = at[start + 260 * var + 256]
+            assert re.search(r"s_branch\s+(\S+)", ins[j][2])
+        assert end in at
+
+
+def test_launch_grids_stay_inside_the_work_item_range():
+    """Every pass's launch (blocks x threads) stays below 2^32 work-items at
+    the largest states: Z-only terms (diagonal sweeps), two-rotation spans and
+    tile passes at n = 34 and 35, both precisions."""
+    rng = np.random.default_rng(5)
+    for n in (34, 35):
+        x = [0, 0, 1 << (n - 1), (1 << (n - 1)) | 1, 3, 1 << (n - 2), 0b101]
+        z = [1, (1 << n) - 1, 0, 1 << (n - 3), 0, 2, 0b111]
+        phi = list(rng.uniform(-0.5, 0.5, size=len(x)))
+        s = P.prx_sched_from_rotations(n, x, z, phi)
+        for dt in (P.PRX_C64, P.PRX_C128):
+            for kern, opts in ((P.PRX_PLAIN, None), (P.PRX_FUSED, None),
+                               (P.PRX_FUSED, dict(span_max=1)), (P.PRX_FUSED, dict(span_max=2)),
+                               (P.PRX_FUSED, dict(tile_qubits=10, chunk_rank=3))):
+                pl = P.prx_plan_create(s, n, dt, 0, len(x), kern, opts)
+                for i in range(P.prx_plan_get_info(pl)["passes"]):
+                    ps = P.prx_plan_pass(pl, i)
+                    assert 0 < ps["grid_blocks"] <= 1 << 22
+                    assert ps["grid_blocks"] * ps["block_threads"] < 1 << 32, (n, dt, ps)
+                P.prx_plan_destroy(pl)
+        P.prx_sched_destroy(s)
+
+
+def test_lambda_is_the_sum_of_magnitudes():
+    """lambda = sum |h_l| (Methods, "Hamiltonian simulation"), pinned to exact
+    values: dyadic coefficients whose magnitudes sum exactly, signs that a
+    dropped absolute value would cancel, and random coefficients against
+    math.fsum (correctly rounded) within the left-to-right rounding bound."""
+    import math
+    from oracle import schedules as S
+    h = [0.5, -0.25, 0.125, -0.0625, 1.0, -2.0]
+    assert S.lambda_of(h) == 3.9375
+    H = P.prx_ham_create(3, [1, 2, 3, 4, 5, 6], [0] * 6, h)
+    assert P.prx_ham_lambda(H) == 3.9375
+    P.prx_ham_destroy(H)
+    rng = np.random.default_rng(11)
+    h = rng.normal(size=500) * np.exp(rng.normal(-4, 2, size=500))
+    exact = math.fsum(abs(v) for v in h)
+    bound = 500 * 2.0 ** -53 * exact
+    assert abs(S.lambda_of(h) - exact) <= bound
+    H = P.prx_ham_create(10, np.arange(1, 501) % 1024, np.zeros(500, np.uint64), h)
+    assert abs(P.prx_ham_lambda(H) - exact) <= bound
+    P.prx_ham_destroy(H)
+
+
+def test_binding_rejects_mismatched_state_tensors():
+    """The binding checks a state tensor before its address crosses the ABI:
+    dtype, element count, contiguity and device (CPU tensors here stand in
+    for every case; the device check comes last)."""
+    import torch
+    ws = torch.empty(256, dtype=torch.uint8)
+    with pytest.raises(TypeError, match="does not match complex64"):
+        P.prx_norm2(torch.zeros(16, dtype=torch.complex128), 4, P.PRX_C64, ws)
+    with pytest.raises(TypeError, match="does not match complex128"):
+        P.prx_amplitude(torch.zeros(16, dtype=torch.complex64), 4, P.PRX_C128, 0)
+    with pytest.raises(ValueError, match="expected 2"):
+        P.prx_amplitude(torch.zeros(8, dtype=torch.complex64), 4, P.PRX_C64, 0)
+    with pytest.raises(ValueError, match="not contiguous"):
+        P.prx_amplitude(torch.zeros(32, dtype=torch.complex64)[::2], 4, P.PRX_C64, 0)
+    with pytest.raises(ValueError, match="not on a GPU"):
+        P.prx_amplitude(torch.zeros(16, dtype=torch.complex64), 4, P.PRX_C64, 0)
+    with pytest.raises(ValueError, match="psi0"):
+        P.prx_overlap(torch.zeros(16, dtype=torch.complex64), 0, 4, P.PRX_C64, 0)
+    s = P.prx_sched_from_rotations(4, [1], [0], [0.1])
+    pl = P.prx_plan_create(s, 4, P.PRX_C128, 0, 1, P.PRX_FUSED)
+    info = P.prx_plan_get_info(pl)
+    assert info["n"] == 4 and info["dtype"] == P.PRX_C128
+    with pytest.raises(TypeError, match="does not match complex128"):
+        P.prx_plan_execute(pl, torch.zeros(16, dtype=torch.complex64), ws)
+    with pytest.raises(ValueError, match="expected 2"):
+        P.prx_apply_range(torch.zeros(32, dtype=torch.complex128), 4, P.PRX_C128, s, 0, 1,
+                          P.PRX_FUSED, ws)
+    P.prx_plan_destroy(pl)
+    b = P.prx_batch_create([6, 7], [P.prx_sched_from_rotations(6, [1], [0], [0.1]),
+                                    P.prx_sched_from_rotations(7, [1], [0], [0.1])],
+                           P.PRX_C64, [0, 0])
+    with pytest.raises(ValueError, match="sample 1"):
+        P.prx_batch_upload(b, [0, torch.zeros(64, dtype=torch.complex64)], ws)
+    with pytest.raises(ValueError, match="2 states for 1"):
+        P.prx_batch_run([0, 0], [6], [s], P.PRX_C64, [0], ws)
+    P.prx_batch_destroy(b)
+    P.prx_sched_destroy(s)
