@@ -1,9 +1,9 @@
 """Robust-phase-estimation signals on top of the rotation engine.
 
-Methods, "Data analysis": for a step size delta the effective Hamiltonian
-of the partially randomised product formula (Eq. hamil_split, second order)
-has its dominant frequency at the effective ground-state energy, and round m
-of robust phase estimation uses the signal
+Methods, "Data analysis"; Eq. hamil_split: at step size delta, the
+second-order partially randomised formula acts like exp(i delta H~(delta)),
+and the frequency that dominates its signal is the lowest eigenvalue of
+H~(delta).  Round m of robust phase estimation evaluates
 
     Z_m = g(delta 2^m) = <psi| exp(i delta H~(delta) 2^m) |psi>,
 
@@ -22,7 +22,14 @@ post-processes the signal on the host:
   prefactor C_gs for the partially randomised split (Methods, "Data
   analysis"), with every deterministic term assumed to anticommute with
   H_R;
-* ``signal`` -- Z_0 .. Z_M on the GPU;
+* ``signal`` -- Z_0 .. Z_M on the GPU, one random sample per round;
+* ``signal_samples`` -- the same rounds with S independent samples each,
+  all samples of a round applied by one batched launch sequence
+  (prx_batch_run); Z_m is then the sample mean, whose magnitude the finite
+  number r of random draws damps (Supplementary, sensitivity to the number
+  of random samples);
+* ``expected_damping`` -- the exact expected magnitude of that mean for
+  commuting terms and a basis eigenstate (a closed form used as a pin);
 * ``estimate`` -- the phase of the dominant frequency, unwrapped round by
   round (each round narrows the previous estimate's 2 pi / (delta 2^m)
   ambiguity), as robust phase estimation does with noiseless signals.
@@ -136,3 +143,80 @@ def signal(x, z, h, psi0, n: int, dtype: int, delta: float, M: int, L_det: int,
     finally:
         P.prx_ham_destroy(H)
     return Z, r
+
+
+def sample_seed(seed: int, m: int, s: int) -> int:
+    """Seed of sample s in round m of ``signal_samples``."""
+    return seed + (m << 20) + s
+
+
+def signal_samples(x, z, h, psi0, n: int, dtype: int, delta: float, M: int, L_det: int,
+                   samples: int, seed: int = 0, r: int | None = None, stream=None):
+    """Z_0 .. Z_M as means over `samples` independent random samples per round.
+
+    Round m runs, for every sample s, 2^m steps of length delta with 2 r
+    random draws per step, seeded with sample_seed(seed, m, s); the samples
+    of a round start from copies of psi0 (a device tensor, left unchanged)
+    and run together through prx_batch_run.  Returns (Z, per_sample, r):
+    Z[m] the mean of <psi0|psi_s>, per_sample[m] the S overlaps."""
+    import torch
+
+    if samples < 1:
+        raise ValueError("samples must be >= 1")
+    D, lam_r = split_weights(h, L_det)
+    if r is None:
+        r = samples_per_stage(delta, lam_r, M) if len(D) < len(h) else 0
+    draws = 2 * r if len(D) < len(h) else 0
+    H = P.prx_ham_create(n, x, z, h)
+    red = torch.empty(P.prx_reduce_workspace_bytes(n), dtype=torch.uint8, device=psi0.device)
+    Z, per = [], []
+    try:
+        for m in range(M + 1):
+            steps = 2 ** m
+            scheds = []
+            try:
+                for smp in range(samples):
+                    scheds.append(P.prx_sched_partial(H, L_det, delta * steps, steps, draws,
+                                                      sample_seed(seed, m, smp),
+                                                      P.PRX_REORDER_SUFFIX))
+                psis = [psi0.clone() for _ in range(samples)]
+                b = P.prx_batch_create([n] * samples, scheds, dtype, [0] * samples)
+                try:
+                    wsb = P.prx_batch_workspace_bytes(b) + 16 * samples + 256
+                finally:
+                    P.prx_batch_destroy(b)
+                ws = torch.empty(wsb, dtype=torch.uint8, device=psi0.device)
+                P.prx_batch_run(psis, [n] * samples, scheds, dtype, [0] * samples, ws, stream)
+                ov = np.array([P.prx_overlap(psi0, p, n, dtype, red, stream) for p in psis])
+                per.append(ov)
+                Z.append(complex(ov.mean()))
+                del psis, ws
+            finally:
+                for sc in scheds:
+                    P.prx_sched_destroy(sc)
+    finally:
+        P.prx_ham_destroy(H)
+    return Z, per, r
+
+
+def expected_damping(h, z, b: int, L_det: int, delta: float, m: int, r: int) -> float:
+    """|E[Z_m]| for Z-only (commuting) terms and the basis state |b>.
+
+    Every rotation multiplies |b> by a phase, so a sample's Z_m has modulus
+    one and only the random phases vary: each of the N = 2 r 2^m draws picks
+    term j with probability |h_j| / lambda_R and contributes the phase
+    exp(i a sgn(h_j) (-1)^popcount(b & z_j)), a = lambda_R delta / (2 r).
+    With mu the probability-weighted mean of those signs, the mean phase of a
+    draw has modulus sqrt(cos^2 a + mu^2 sin^2 a), hence
+        |E[Z_m]| = (1 - (1 - mu^2) sin^2 a)^(N / 2)."""
+    z = [int(v) for v in np.asarray(z, dtype=np.uint64)]
+    h = np.asarray(h, dtype=np.float64)
+    D, lam_r = split_weights(h, L_det)
+    rest = sorted(set(range(len(h))) - set(D))
+    if not rest or r == 0:
+        return 1.0
+    mu = sum(abs(h[j]) * math.copysign(1.0, h[j]) * (-1.0) ** bin(b & z[j]).count("1")
+             for j in rest) / lam_r
+    a = lam_r * delta / (2 * r)
+    N = 2 * r * 2 ** m
+    return (1.0 - (1.0 - mu * mu) * math.sin(a) ** 2) ** (N / 2)

@@ -22,8 +22,8 @@ Cases:
                  N = 2000 draws, t = 1, sample i seeded with i) from the basis
                  state with the low floor(n/2) bits set.  Stores every
                  sample's overlap <k0|psi> and squared norm, and for the first
-                 sample of each n, in ``.npz``, the amplitudes at up to 2^14
-                 distinct uniform indices (``default_rng(n)``) plus the 1024
+                 sample of each n, in ``.npz``, the amplitudes at up to 2^12
+                 distinct uniform indices (``default_rng(n)``) plus the 256
                  largest.  Samples are run smallest n first and the file is
                  rewritten after each one, so an interrupted run resumes.
 """
@@ -174,7 +174,7 @@ def qdrift_batch():
         rec["norm2"][i] = sv.c_norm2(out)
         rec["oracle_seconds"] = round(rec["oracle_seconds"] + dt, 1)
         if reps[n] == i:
-            idx, vals = _amplitude_sample(out, n, 1 << 14, 1024, n)
+            idx, vals = _amplitude_sample(out, n, 1 << 12, 256, n)
             fname = f"qdrift_batch_n{n}.npz"
             np.savez(os.path.join(HERE, fname), idx=idx, re=vals.real, im=vals.imag)
             rec["representatives"][str(n)] = {"sample": i, "amplitudes": fname}

@@ -75,3 +75,45 @@ def test_split_weights_matches_schedule_split():
         D2, R2 = partial_split(h, L_det)
         assert D == D2
         assert lam_r == pytest.approx(float(np.sum(np.abs(h[R2]))) if R2 else 0.0)
+
+
+def _zonly(n, L, seed):
+    rng = np.random.default_rng(seed)
+    z = rng.integers(1, 1 << n, size=L).astype(np.uint64)
+    return np.zeros(L, dtype=np.uint64), z, rng.normal(scale=0.5, size=L)
+
+
+@pytest.mark.parametrize("r", [1, 16])
+def test_damping_closed_form_against_oracle_samples(r):
+    """Supplementary, sensitivity to the number of random samples: fewer
+    random draws damp the sample-mean signal.  For Z-only terms and a basis
+    state every sample is a pure phase, and the mean over many oracle runs
+    (schedules re-expanded by the oracle, states by its numpy loop) matches the
+    closed form of rpe.expected_damping within the sampling error; the
+    closed form itself falls as r shrinks."""
+    import synth
+    from oracle import schedules as osch
+    from oracle import statevector as sv
+    n, L, L_det, delta, m, S = 6, 12, 4, 0.5, 3, 1000
+    x, z, h = _zonly(n, L, 3)
+    b = synth.basis_index(n)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[b] = 1.0
+    acc = 0.0 + 0.0j
+    for s in range(S):
+        rx, rz, rp = osch.partial(x, z, h, L_det, delta * 2 ** m, 2 ** m, 2 * r,
+                                  rpe.sample_seed(9, m, s), suffix=True)
+        out = sv.apply_rotations(psi0, rx, rz, rp)
+        assert abs(abs(out[b]) - 1.0) <= 1e-12
+        acc += out[b]
+    mean = abs(acc / S)
+    want = rpe.expected_damping(h, z, b, L_det, delta, m, r)
+    assert abs(mean - want) <= 0.1, (mean, want)
+    assert rpe.expected_damping(h, z, b, L_det, delta, m, 1) < \
+        rpe.expected_damping(h, z, b, L_det, delta, m, 4) < \
+        rpe.expected_damping(h, z, b, L_det, delta, m, 16) < 1.0
+
+
+def test_damping_without_random_part_is_one():
+    x, z, h = _zonly(6, 12, 3)
+    assert rpe.expected_damping(h, z, 7, 12, 0.5, 4, 0) == 1.0
