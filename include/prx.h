@@ -286,6 +286,24 @@ prx_status prx_apply_range(void *psi, int n, prx_dtype dtype, const prx_sched *s
                            size_t begin, size_t end, prx_kernel kernel, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * prx_apply_range, but the plan workspace is a library-owned static device
+ * buffer of PRX_STATIC_WS_BYTES per GPU (held until the process ends) in
+ * place of a caller workspace.  The call allocates no device memory.
+ *   psi    device, 2^n contiguous elements of dtype, updated in place;
+ *   stream hipStream_t (NULL = default stream); the call waits for it.
+ * INVALID when the plan's workspace (prx_plan_info.workspace_bytes, as
+ * prx_workspace_bytes reports for the same range) exceeds the buffer,
+ * before any device work; otherwise as prx_apply_range.  Every call on one
+ * GPU uses that GPU's one buffer: the library serialises its own calls with
+ * a lock, and work that overlaps a call on the same GPU through any other
+ * path that uses the buffer would race.  Nothing in the buffer needs to
+ * start at zero: each call writes every byte it later reads. */
+#define PRX_STATIC_WS_BYTES (64u << 20)
+prx_status prx_apply_range_static(void *psi, int n, prx_dtype dtype, const prx_sched *sched,
+                                  size_t begin, size_t end, prx_kernel kernel, void *stream);
+
 /* Workspace bytes the reductions need for a 2^n state. */
 size_t prx_reduce_workspace_bytes(int n);
 

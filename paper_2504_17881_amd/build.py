@@ -22,7 +22,7 @@ LIB = os.path.join(LIBDIR, "libprx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["sched.cpp", "plan.cpp", "kernels.hip", "batch.hip", "tune.cpp"]
+SOURCES = ["sched.cpp", "plan.cpp", "kernels.hip", "batch.hip", "tune.cpp", "noalloc.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

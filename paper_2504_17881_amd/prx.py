@@ -136,6 +136,7 @@ _sig("prx_plan_chunk", _st, _vp, _sz, ctypes.POINTER(prx_chunk_info))
 _sig("prx_plan_rotation", _st, _vp, _sz, ctypes.POINTER(prx_rot_info))
 _sig("prx_workspace_bytes", _sz, _i, _i, _vp, _i)
 _sig("prx_apply_range", _st, _vp, _i, _i, _vp, _sz, _sz, _i, _vp, _sz, _vp)
+_sig("prx_apply_range_static", _st, _vp, _i, _i, _vp, _sz, _sz, _i, _vp)
 _sig("prx_reduce_workspace_bytes", _sz, _i)
 _sig("prx_overlap", _st, _vp, _vp, _i, _i, _dp, _vp, _sz, _vp)
 _sig("prx_amplitude", _st, _vp, _i, _i, ctypes.c_uint64, _dp, _vp)
@@ -434,6 +435,15 @@ def prx_apply_range(psi, n: int, dtype: int, sched: int, begin: int, end: int, k
                     ws, stream=None, ws_bytes=None) -> None:
     _check(_lib.prx_apply_range(_state(psi, n, dtype), n, dtype, sched, begin, end, kernel,
                                 _device_buf(ws), _nbytes(ws, ws_bytes), _stream(stream)))
+
+
+PRX_STATIC_WS_BYTES = 64 << 20
+
+
+def prx_apply_range_static(psi, n: int, dtype: int, sched: int, begin: int, end: int,
+                           kernel: int, stream=None) -> None:
+    _check(_lib.prx_apply_range_static(_state(psi, n, dtype), n, dtype, sched, begin, end,
+                                       kernel, _stream(stream)))
 
 
 def prx_reduce_workspace_bytes(n: int) -> int:
