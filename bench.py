@@ -4,9 +4,12 @@
 Workload (precision workload): synthetic Jordan-Wigner-shaped Hamiltonian,
 n = 32, L = 5000 terms (seed 0), lexicographically ordered terms,
 first-order Trotter with t = 0.5 and 4 steps (2*10^4 rotations), initial
-basis state with the low 16 bits set.  One bench step is one Trotter step
-(5000 rotations) applied by the fused complex64 path with FP64
-renormalisation, followed by the overlap with the initial basis state.
+basis state with the low 16 bits set.  Every Trotter step is the same
+5000-rotation product, so one plan serves all steps.  A bench step is one
+Trotter step applied by the fused complex64 path with FP64 renormalisation,
+followed by the overlap with the initial basis state; the timed loop applies
+K consecutive steps to one state (steps 1-4 are the workload's run, later
+steps continue it).
 
 Reported:
   value        amplitude updates per second of the timed steps
@@ -15,10 +18,16 @@ Reported:
                kernel time): algorithmic bytes per launch (2 * 2^n * 8 B,
                one read and one write of the state) over its average
                launch duration from HIP events recorded around every pass;
+  precision    outside the timed region: the whole 4-step run in complex64
+               (fused) and in complex128 (fused, tuned), both resident;
+               amplitude 2-norm error and |overlap difference| of complex64
+               against complex128 after 10^4 rotations and at the end, and
+               the complex128 run's own rate and roofline;
   fp64_plain   the complex128 single-rotation sweep on the same schedule
                (first `--plain-rotations` rotations), for the 2x comparison;
   cpu_baseline the FP64 CPU oracle on the first rotations of the same
-               schedule and state, on this host's cores.
+               schedule and state on all host cores, plus one core and the
+               n = 28 Trotter workload's 100-rotation rate.
 
     python bench.py [--gpus 1] [--steps 4] [--warmup 1]
 """
@@ -74,31 +83,91 @@ def read_traffic(kernel: str):
         return None
 
 
-def cpu_baseline(x, z, phi, n: int, k0: int, budget_s: float, max_rot: int):
-    """The oracle as it stands, on the first rotations of the schedule."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(x, z, phi, n: int, k0: int, budget_s: float, max_rot: int):
+    """Applies rotation 0 untimed (it also first-touches the state and the
+    oracle's scratch array), then rotations 1, 2, ... one by one until the
+    budget is spent; returns (timed rotations, seconds, threads)."""
     import numpy as np
     sys.path.insert(0, ROOT)
     from oracle import statevector as sv
     psi = np.zeros(1 << n, dtype=np.complex128)
     psi[k0] = 1.0
     work = np.empty_like(psi)
+    sv.c_apply_rotations(psi, x[0:1], z[0:1], phi[0:1], out=psi, work=work)
     done = 0
     t0 = time.perf_counter()
     while done < max_rot:
-        sv.c_apply_rotations(psi, x[done:done + 1], z[done:done + 1], phi[done:done + 1],
-                             out=psi, work=work)
+        r = done + 1
+        sv.c_apply_rotations(psi, x[r:r + 1], z[r:r + 1], phi[r:r + 1], out=psi, work=work)
         done += 1
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
-    return {
+    return done, time.perf_counter() - t0, sv.c_threads()
+
+
+def _trotter1_n28_rotations():
+    """The n = 28 Trotter workload's schedule (given term order), re-expanded
+    by the oracle's schedule builder."""
+    sys.path.insert(0, ROOT)
+    import synth
+    from oracle import schedules as osch
+    w = synth.WORKLOADS["trotter1_n28"]
+    x, z, h = synth.jw_hamiltonian(w["n"], w["L"], w["ham_seed"])
+    rx, rz, rp = osch.trotter(x, z, h, 1, w["t"], w["steps"], suffix=False)
+    return w["n"], rx, rz, rp, synth.basis_index(w["n"])
+
+
+def one_core_worker(budget_s: float) -> int:
+    """Child process (OMP_NUM_THREADS=1): the oracle on one core, first
+    rotations of the n = 28 Trotter workload; prints one JSON line."""
+    n, rx, rz, rp, k0 = _trotter1_n28_rotations()
+    done, dt, thr = _oracle_rate(rx, rz, rp, n, k0, budget_s, 100)
+    print(json.dumps({"rotations": done, "seconds": dt, "threads": thr, "n": n}))
+    return 0
+
+
+def cpu_baseline(x, z, phi, n: int, k0: int, budget_s: float, max_rot: int):
+    """The oracle as it stands: all cores on the first rotations of the
+    benchmark schedule; one core (child process) and all cores on the n = 28
+    Trotter workload's first rotations (at most 100)."""
+    import subprocess
+    done, dt, thr = _oracle_rate(x, z, phi, n, k0, budget_s, max_rot)
+    out = {
         "value": done * float(1 << n) / dt,
         "unit": "amplitude-updates/s",
-        "cores": sv.c_threads(),
+        "cores": thr,
         "kind": "oracle",
-        "sample": (f"first {done} rotation(s) of the same n={n} schedule from the same basis "
-                   f"state, FP64 C oracle (scatter form, OpenMP), {dt:.1f} s"),
+        "sample": (f"rotations 1..{done} of the same n={n} schedule from the same basis "
+                   f"state (rotation 0 untimed), FP64 C oracle (scatter form, OpenMP), "
+                   f"{dt:.1f} s"),
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
     }
+    n28, rx, rz, rp, b28 = _trotter1_n28_rotations()
+    d2, t2, thr2 = _oracle_rate(rx, rz, rp, n28, b28, budget_s, 100)
+    out["n28_rate"] = {"value": d2 * float(1 << n28) / t2, "cores": thr2, "rotations": d2,
+                       "seconds": t2, "sample": "rotations 1.. of the n=28 Trotter workload (rotation 0 untimed)"}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--one-core-worker",
+                        "--cpu-budget", str(budget_s / 2)], env=env, capture_output=True,
+                       text=True, timeout=600)
+    if r.returncode == 0 and r.stdout.strip():
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        out["one_core"] = {"value": one["rotations"] * float(1 << one["n"]) / one["seconds"],
+                           "cores": one["threads"], "rotations": one["rotations"],
+                           "seconds": one["seconds"],
+                           "sample": "rotations 1.. of the n=28 Trotter workload (rotation 0 untimed)"}
+    return out
 
 
 def fusion_sweep(ns, reps: int) -> int:
@@ -229,6 +298,21 @@ def batch_workload(steps: int, warmup: int) -> int:
     return 0
 
 
+def _diff_norm(a, b, chunk=1 << 26) -> float:
+    """||a - b||_2 in FP64, chunk by chunk (no full-size temporaries)."""
+    import torch
+    acc = 0.0
+    for s0 in range(0, a.numel(), chunk):
+        d = a[s0:s0 + chunk].to(torch.complex128) - b[s0:s0 + chunk].to(torch.complex128)
+        acc += float(torch.sum(d.real * d.real + d.imag * d.imag))
+    return acc ** 0.5
+
+
+def _dominant(per_kernel: dict):
+    name, (cnt, ms) = max(per_kernel.items(), key=lambda kv: kv[1][1])
+    return name, cnt, ms / cnt
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,7 +323,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--fused-only", action="store_true",
-                    help="skip the FP64-plain comparator (profiling runs)")
+                    help="skip the FP64-plain comparator and the precision leg (profiling runs)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the complex64-against-complex128 whole-run leg")
+    ap.add_argument("--one-core-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="autotune cache (JSON) loaded before planning; plans use PRX_AUTO")
     ap.add_argument("--autotune-save", default=None,
@@ -261,6 +348,8 @@ def main() -> int:
                     help="instead of the benchmark, time the qDRIFT batching workload "
                          "(256 samples in one graph)")
     args = ap.parse_args()
+    if args.one_core_worker:
+        return one_core_worker(args.cpu_budget)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the hot path is a "
               "single-device kernel and this build has no multi-GPU path.", file=sys.stderr)
@@ -271,19 +360,31 @@ def main() -> int:
         return batch_workload(max(1, args.steps), max(0, args.warmup))
 
     import numpy as np
-    import torch
     sys.path.insert(0, ROOT)
     import synth
-    from paper_2504_17881_amd import prx as P
 
     w = synth.WORKLOADS["trotter1_n32"]
     n = args.n
     L, t, S = w["L"], w["t"], w["steps"]
     x, z, h = synth.jw_hamiltonian(n, L, w["ham_seed"])
+    k0 = synth.basis_index(n)
+
+    # ---------------- CPU baseline first, before anything touches the GPU
+    # (its one-core leg runs in a child process)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import schedules as osch
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        ox, oz, op = osch.trotter(x, z, h, 1, t, S, suffix=True)
+        cpu = cpu_baseline(ox, oz, op, n, k0, args.cpu_budget, 4)
+        del ox, oz, op
+
+    import torch
+    from paper_2504_17881_amd import prx as P
+
     H = P.prx_ham_create(n, x, z, h)
     sched = P.prx_sched_trotter(H, 1, t, S, P.PRX_REORDER_SUFFIX)
     _, sx, sz, sphi = P.prx_sched_view(sched)
-    k0 = synth.basis_index(n)
     dev = torch.device("cuda:0")
     print(f"[bench] n={n} L={L} rotations={len(sx)}", file=sys.stderr, flush=True)
 
@@ -300,7 +401,6 @@ def main() -> int:
         torch.cuda.empty_cache()
 
     # ---------------- planner settings: tuned cache (or a fresh tuning run)
-    tuned = None
     if args.tune_cache and os.path.exists(args.tune_cache):
         P.prx_autotune_load(args.tune_cache)
     if args.autotune_save:
@@ -334,23 +434,25 @@ def main() -> int:
     P.prx_plan_upload(plan, ws)
     psi = torch.zeros(1 << n, dtype=torch.complex64, device=dev)
     psi[k0] = 1.0
-    bra = k0
     torch.cuda.synchronize()
     for _ in range(args.warmup):
         P.prx_plan_execute_timed(plan, psi, ws)
-        P.prx_amplitude(psi, n, P.PRX_C64, bra)
+        P.prx_amplitude(psi, n, P.PRX_C64, k0)
+    # the timed steps start from the workload's initial state
+    psi.zero_()
+    psi[k0] = 1.0
     torch.cuda.synchronize()
     print(f"[bench] fused c64: {info['passes']} passes/step, mean fuse "
           f"{info['mean_fuse']:.2f}", file=sys.stderr, flush=True)
 
     per_kernel = {}
     renorm_total = 0.0
-    ov = None
+    ovs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         pm, rm = P.prx_plan_execute_timed(plan, psi, ws)
-        ov = P.prx_amplitude(psi, n, P.PRX_C64, bra)  # <k0|psi>
+        ovs.append(P.prx_amplitude(psi, n, P.PRX_C64, k0))  # <k0|psi>
         for nm, ms in zip(names, pm):
             a = per_kernel.setdefault(nm, [0, 0.0])
             a[0] += 1
@@ -360,16 +462,77 @@ def main() -> int:
     wall = time.perf_counter() - t0
     updates = args.steps * L * float(1 << n)
     value = updates / wall
-    state_bytes = float(1 << n) * 8
-    bytes_per_pass = 2.0 * state_bytes
-    dom = max(per_kernel.items(), key=lambda kv: kv[1][1])
-    dom_name, (dom_cnt, dom_ms) = dom
-    dom_avg_ms = dom_ms / dom_cnt
+    bytes_per_pass = 2.0 * float(1 << n) * 8
+    dom_name, dom_cnt, dom_avg_ms = _dominant(per_kernel)
     achieved = bytes_per_pass / (dom_avg_ms * 1e-3) / 1e9
     traffic = read_traffic(dom_name)
     all_pass_bw = args.steps * info["passes"] * bytes_per_pass / wall / 1e9
+    del psi
+    torch.cuda.empty_cache()
+    print(f"[bench] timed: {wall / args.steps * 1e3:.1f} ms per step, {dom_name} "
+          f"{dom_avg_ms:.2f} ms per launch", file=sys.stderr, flush=True)
+
+    # ---------------- precision leg (outside the timed region): the whole run
+    # in complex64 fused against complex128 fused, both resident
+    precision = None
+    if not (args.fused_only or args.no_precision):
+        print("[bench] precision leg: complex64 against complex128 over the whole run",
+              file=sys.stderr, flush=True)
+        tuned128 = P.prx_autotune_lookup(n, P.PRX_C128)
+        plan128 = P.prx_plan_create(sched, n, P.PRX_C128, 0, L,
+                                    P.PRX_AUTO if tuned128 else P.PRX_FUSED)
+        info128 = P.prx_plan_get_info(plan128)
+        names128 = [kernel_symbol(P.prx_plan_pass(plan128, i), "double")
+                    for i in range(info128["passes"])]
+        ws128 = torch.empty(info128["workspace_bytes"], dtype=torch.uint8, device=dev)
+        P.prx_plan_upload(plan128, ws128)
+        a = torch.zeros(1 << n, dtype=torch.complex64, device=dev)
+        b = torch.zeros(1 << n, dtype=torch.complex128, device=dev)
+        a[k0] = 1.0
+        b[k0] = 1.0
+        torch.cuda.synchronize()
+        rows, k128, wall128 = [], {}, 0.0
+        for step in range(1, S + 1):
+            P.prx_plan_execute_timed(plan, a, ws)
+            tb0 = time.perf_counter()
+            pm, _ = P.prx_plan_execute_timed(plan128, b, ws128)
+            wall128 += time.perf_counter() - tb0
+            for nm, ms in zip(names128, pm):
+                e = k128.setdefault(nm, [0, 0.0])
+                e[0] += 1
+                e[1] += float(ms)
+            if step * L == 10000 or step == S:
+                oa = P.prx_amplitude(a, n, P.PRX_C64, k0)
+                ob = P.prx_amplitude(b, n, P.PRX_C128, k0)
+                rows.append({"rotations": step * L, "err_l2": _diff_norm(a, b),
+                             "d_overlap": abs(oa - ob), "overlap_c128": [ob.real, ob.imag],
+                             "overlap_c64": [oa.real, oa.imag]})
+                print(f"[bench] precision at {step * L} rotations: err_l2 "
+                      f"{rows[-1]['err_l2']:.3e} |d overlap| {rows[-1]['d_overlap']:.3e}",
+                      file=sys.stderr, flush=True)
+        d128, c128, avg128 = _dominant(k128)
+        bpp128 = 2.0 * float(1 << n) * 16
+        ach128 = bpp128 / (avg128 * 1e-3) / 1e9
+        precision = {
+            "reference": "complex128 fused (tuned) over the same schedule from the same state",
+            "at": rows,
+            "err_l2": rows[-1]["err_l2"], "d_overlap": rows[-1]["d_overlap"],
+            "fp64_fused": {
+                "value": S * L * float(1 << n) / wall128, "unit": "amplitude-updates/s",
+                "passes_per_step": info128["passes"],
+                "planner": ({k: v for k, v in tuned128.items() if v} if tuned128
+                            else "defaults"),
+                "roofline": {"bound": "hbm", "achieved": ach128, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": ach128 / HBM_PEAK_GBS, "kernel": d128,
+                             "launches": c128, "avg_launch_ms": avg128,
+                             "bytes_per_launch": bpp128},
+            },
+        }
+        P.prx_plan_destroy(plan128)
+        del a, b, ws128
+        torch.cuda.empty_cache()
     P.prx_plan_destroy(plan)
-    del psi, ws
+    del ws
     torch.cuda.empty_cache()
 
     # ---------------- FP64 plain comparator (complex128, one sweep per rotation)
@@ -408,11 +571,7 @@ def main() -> int:
         del psi2, pws, wws
         torch.cuda.empty_cache()
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(sx, sz, sphi, n, k0, args.cpu_budget, 4)
-
+    run_steps = min(S, args.steps)
     out = {
         "metric": METRIC,
         "value": value,
@@ -428,9 +587,13 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": (f"trotter1_n{n}: synthetic JW-shaped H, n={n}, L={L}, first-order "
-                         f"Trotter t={t}, {S} steps in the run, lexicographic (SUFFIX) term "
-                         "order, complex64 fused with FP64 renormalisation; one step = one "
-                         "Trotter step (5000 rotations) + basis overlap"),
+                         f"Trotter t={t}, {S} steps ({S * L} rotations), lexicographic (SUFFIX) "
+                         "term order, from the basis state with the low 16 bits set; complex64 "
+                         "fused with FP64 renormalisation.  One bench step = one Trotter step "
+                         f"({L} rotations; every step is the same product) + the basis "
+                         f"overlap; the timed loop applies {args.steps} consecutive steps to "
+                         f"one state (steps 1-{S} are the workload's run, later steps "
+                         "continue it)"),
             "n": n, "L": L, "rotations_per_step": L,
             "passes_per_step": info["passes"], "mean_fuse": info["mean_fuse"],
             "span_passes": info["span_passes"], "tile_passes": info["tile_passes"],
@@ -453,7 +616,12 @@ def main() -> int:
         "kernels": {k: {"launches": c, "total_ms": ms, "avg_ms": ms / c}
                     for k, (c, ms) in sorted(per_kernel.items())},
         "renorm_ms_total": renorm_total,
-        "overlap_final": [ov.real, ov.imag] if ov is not None else None,
+        "overlap_run_end": ([ovs[run_steps - 1].real, ovs[run_steps - 1].imag]
+                            if args.steps >= S else None),
+        "overlap_last_step": [ovs[-1].real, ovs[-1].imag] if ovs else None,
+        "err_l2": precision["err_l2"] if precision else None,
+        "d_overlap": precision["d_overlap"] if precision else None,
+        "precision": precision,
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
     }

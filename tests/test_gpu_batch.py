@@ -1,9 +1,13 @@
 """Tests of the first batched design: one persistent kernel pulling (sample,
 pass, slice) items from an atomic queue, with per-sample completion counters
 that later items waited on.  Its first GPU run did not complete (the test
-timed out inside the kernel), and so did the one run of a revised wait loop;
-the cause was not shown, so that design was switched off (removed from the
-library) and these tests are skipped.  The batched path the library now
+timed out inside the kernel), and so did the one run of a revised wait loop,
+so that design was switched off (removed from the library) and these tests
+are skipped.  The cause was found later on the CPU, in the gfx950 code of the
+same constructs: each spin iteration's acquire load invalidated its XCD's
+whole L2 (buffer_inv sc1) and each finished item wrote the L2 back twice
+(buffer_wbl2 sc1), which with ~1000 waiting workgroups collapses throughput,
+while the iteration-count bound on a wait exceeded the test's time limit.  The batched path the library now
 builds (one kernel per pass round, no cross-workgroup waits) is tested in
 tests/test_gpu_batch_rounds.py.
 """
@@ -20,7 +24,7 @@ from oracle import statevector as sv
 from paper_2504_17881_amd import prx as P
 from gpu_util import apply, basis_state, dev, rel_err, tdtype, to_dev, to_host, workspace
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="queue-based persistent batch kernel with cross-workgroup waits did not finish on the GPU twice; cause not shown; design switched off")]
+pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="queue-based persistent batch kernel with cross-workgroup waits did not finish on the GPU twice (per-iteration L2 invalidation in its spin waits); design switched off")]
 
 EPS32 = 2.0 ** -24
 
