@@ -51,6 +51,8 @@ def kernel_symbol(ps: dict, dtype_name: str) -> str:
         return f"k_span<{dtype_name},{ps['m']}>"
     if ps["kind"] == 2:
         return f"k_tile<{dtype_name},{ps['B']},{ps['m']}>"
+    if ps["kind"] == 3:
+        return f"k_permute<{dtype_name}>"
     return f"k_plain<{dtype_name}>"
 
 
@@ -222,6 +224,60 @@ def fusion_sweep(ns, reps: int) -> int:
     return 0
 
 
+def relabel_compare(reps: int) -> int:
+    """Qubit relabelling against none, on random-order sequences (one JSON line
+    each): a qDRIFT sample of the batching workload's n = 24 Hamiltonian
+    (2000 draws, complex64, 14-qubit tile-sets) and the random part of one
+    step of the large-state workload (n = 34, 1000 draws, complex64, 12- and
+    14-qubit tile-sets): passes, relabelling passes and the time per
+    application (HIP events around every pass, best of `reps`)."""
+    import torch
+    sys.path.insert(0, ROOT)
+    import synth
+    from paper_2504_17881_amd import prx as P
+    dev = torch.device("cuda:0")
+    cases = []
+    x, z, h = synth.jw_hamiltonian(24, 500, 1024)
+    H24 = P.prx_ham_create(24, x, z, h)
+    cases.append(("qdrift_n24", 24, P.prx_sched_qdrift(H24, 1.0, 2000, 3), 0, 2000, 14, 10))
+    w = synth.WORKLOADS["partial_n34"]
+    x, z, h = synth.jw_hamiltonian(34, w["L"], w["ham_seed"])
+    H34 = P.prx_ham_create(34, x, z, h)
+    s34 = P.prx_sched_partial(H34, w["L_det"], w["t"], w["steps"], w["r"], 0,
+                              P.PRX_REORDER_SUFFIX)
+    r0 = w["L_det"]  # step 1: D forward, then the random draws
+    for B, G in ((12, 8), (14, 10)):
+        cases.append((f"partial_n34_random_step1_B{B}", 34, s34, r0, r0 + w["r"], B, G))
+    for name, n, sch, b, e, B, G in cases:
+        psi = torch.zeros(1 << n, dtype=torch.complex64, device=dev)
+        psi[synth.basis_index(n)] = 1.0
+        for rl in (0, 1):
+            pl = P.prx_plan_create(sch, n, P.PRX_C64, b, e, P.PRX_FUSED,
+                                   dict(tile_qubits=B, max_virtual=G, relabel=rl))
+            info = P.prx_plan_get_info(pl)
+            ws = torch.empty(max(info["workspace_bytes"], 256), dtype=torch.uint8, device=dev)
+            P.prx_plan_upload(pl, ws)
+            P.prx_plan_execute_timed(pl, psi, ws)
+            best = None
+            for _ in range(max(1, reps)):
+                pm, rm = P.prx_plan_execute_timed(pl, psi, ws)
+                ms = float(pm.sum() + rm.sum())
+                best = ms if best is None else min(best, ms)
+            print(json.dumps({"case": name, "n": n, "rotations": e - b, "tile_qubits": B,
+                              "relabel": rl, "passes": info["passes"],
+                              "relabel_passes": info["relabel_passes"], "ms": best}),
+                  flush=True)
+            P.prx_plan_destroy(pl)
+            del ws
+        del psi
+        torch.cuda.empty_cache()
+    P.prx_sched_destroy(cases[0][2])
+    P.prx_sched_destroy(s34)
+    P.prx_ham_destroy(H24)
+    P.prx_ham_destroy(H34)
+    return 0
+
+
 def batch_workload(steps: int, warmup: int) -> int:
     """The batching workload: 256 qDRIFT samples with n uniform on 16..24
     (per-size JW Hamiltonian, L = 500, N = 2000 draws, t = 1), complex64,
@@ -347,6 +403,9 @@ def main() -> int:
     ap.add_argument("--batch-workload", action="store_true",
                     help="instead of the benchmark, time the qDRIFT batching workload "
                          "(256 samples in one graph)")
+    ap.add_argument("--relabel-compare", action="store_true",
+                    help="instead of the benchmark, compare plans with and without qubit "
+                         "relabelling on random-order sequences")
     args = ap.parse_args()
     if args.one_core_worker:
         return one_core_worker(args.cpu_budget)
@@ -358,6 +417,8 @@ def main() -> int:
         return fusion_sweep([int(v) for v in args.sweep_n.split(",")], max(1, args.steps))
     if args.batch_workload:
         return batch_workload(max(1, args.steps), max(0, args.warmup))
+    if args.relabel_compare:
+        return relabel_compare(max(1, args.steps))
 
     import numpy as np
     sys.path.insert(0, ROOT)

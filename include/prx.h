@@ -156,6 +156,11 @@ typedef struct {
     int tile_only;       /* 1: every pass a tile pass, as batched samples of >= tile_qubits
                             qubits are planned (default 0); INVALID with PRX_PLAIN or
                             n < tile_qubits */
+    int relabel;         /* 1: fused plans may insert qubit-relabelling passes (kind 3) that
+                            bring the qubits the next rotations act on into the low index
+                            bits, which every tile pass keeps in its frame; the last pass
+                            restores the original order (default 0; needs n >= 14 and
+                            n >= tile_qubits + 2, otherwise ignored) */
 } prx_plan_opts;
 
 /* Summary of a plan. */
@@ -171,6 +176,7 @@ typedef struct {
     int tile_qubits, chunk_rank;
     int n;                    /* qubits of the state the plan applies to */
     int dtype;                /* prx_dtype of that state */
+    size_t relabel_passes;    /* qubit-relabelling sweeps (kind 3) */
 } prx_plan_info;
 
 /* Segments rotations [begin, end) of `sched` for a 2^n state of `dtype`
@@ -208,7 +214,10 @@ prx_status prx_plan_execute_timed(const prx_plan *plan, void *psi, void *ws, siz
  * frame of B bits = b low qubits + g virtual qubits; workgroup w holds the
  * tiles t XOR (XOR of vmask[i] over the bits i set in v) for v < 2^g, t = w
  * with zeros inserted at the ascending `tpivot` bits of the tile index;
- * chunks [chunk_begin, +count)).
+ * chunks [chunk_begin, +count)), 3 = qubit relabelling (the index bit
+ * perm_pos[j] of every amplitude moves to bit perm_pos[perm_dst[j]], in
+ * place; bits outside perm_pos stay; the rotations after it carry masks in
+ * the new bit order, which the plan's last pass restores).
  * `scale` is the product of the pass's cosines, applied at its store. */
 typedef struct {
     int kind;
@@ -226,6 +235,8 @@ typedef struct {
                                          persistent tile launches, which use the resident
                                          count); the kernels stride over the rest */
     unsigned block_threads;           /* threads per workgroup */
+    uint32_t perm_pos[12];            /* relabelling: the moved bit positions (ascending) */
+    uint32_t perm_dst[12];            /* relabelling: bit perm_pos[j] -> perm_pos[perm_dst[j]] */
 } prx_pass_info;
 
 /* A chunk of a tile pass: basis directions in the workgroup frame; thread t
@@ -239,7 +250,9 @@ typedef struct {
     size_t rot_begin, rot_count;
 } prx_chunk_info;
 
-/* A kernel rotation: (x, z, phi) as applied (fused plans apply a rotation
+/* A kernel rotation: (x, z, phi) as applied, in the index-bit order in
+ * force where it runs (relabelled plans: after the preceding relabelling
+ * passes); fused plans apply a rotation
  * with |tan phi| > 1/sqrt(2) as k equal pieces), its schedule index, and
  * its record: z in the kernel's frame, the tile-index part zhigh, basis slot
  * (15 = diagonal), whether tau = i^{nY+1} tan(phi) is imaginary, zeta (bit

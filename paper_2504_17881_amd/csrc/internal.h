@@ -136,6 +136,23 @@ struct PlainArgs {
     double beta;     // signed magnitude of beta
 };
 
+// Arguments of a qubit-relabelling pass: a permutation of the index bits
+// at the kPermBits positions pos[0..11] (ascending; pos[j] = j for j < 4,
+// the 16 contiguous amplitudes that coalesce one access), all other bits
+// fixed.  Group coordinate s in [0, 2^12) has bit j at index bit pos[j];
+// the element at input coordinate s moves to output coordinate D(s), which
+// has bit dst[j] set for every bit j of s.  The kernel needs, for output
+// coordinate s' = t + 256 u (thread t, slot u), the input coordinate
+// D^-1(s') = D^-1(t) XOR D^-1(256 u); inv[j] is D^-1 of bit j, and ioff[u]
+// = D^-1(256 u) is precomputed on the host.
+static constexpr int kPermBits = 12;
+struct PermArgs {
+    uint32_t pos[kPermBits];
+    uint16_t inv[kPermBits];
+    uint16_t ioff[16];
+    int n;
+};
+
 // Autotune cache (tune.cpp), keyed by (arch, n, dtype).
 bool tune_lookup(int n, prx_dtype dt, prx_plan_opts *out);
 void tune_store(int n, prx_dtype dt, const prx_plan_opts &o);
@@ -154,6 +171,10 @@ hipError_t launch_span(prx_dtype dt, int m, void *psi, const SpanArgs &a, const 
 hipError_t launch_tile(prx_dtype dt, int B, int m, void *psi, const TileArgs &a,
                        const void *rots, const ChunkRec *chunks, const double *renorm_in,
                        double *norm_out, hipStream_t s, unsigned *blocks_out);
+// Qubit relabelling: one pass over the state, in place (every 2^12-element
+// group is closed under the permutation).
+hipError_t launch_permute(prx_dtype dt, void *psi, const PermArgs &a, hipStream_t s);
+unsigned permute_blocks(int n);
 // partial sums -> 1/sqrt(sum) into scale_out[0]; scale_out[1 .. kRenormStage]
 // is stage-1 scratch (two fixed-shape kernels, deterministic)
 static constexpr unsigned kRenormStage = 128;

@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256) k_span(Cx<T> *__restrict__ psi, SpanArgs 
         }
         apply_rots<T, M>(amp, k0, 0, rots + a.rot_begin, a.rot_count);
         if (live) {
-            T part = 0;  // the thread's 2^M squares in the state's precision
+            // the thread's 2^M squares, each exact in FP64, summed in FP64
 #pragma unroll
             for (int v = 0; v < (1 << M); ++v) {
                 const T s = (T)(sc * F[v]);
@@ -154,10 +154,9 @@ __global__ void __launch_bounds__(256) k_span(Cx<T> *__restrict__ psi, SpanArgs 
                 o.re = amp[v].re * s;
                 o.im = amp[v].im * s;
                 psi[k0 ^ X[v]] = o;
-                part = fma(o.re, o.re, part);
-                part = fma(o.im, o.im, part);
+                nrm = fma((double)o.re, (double)o.re, nrm);
+                nrm = fma((double)o.im, (double)o.im, nrm);
             }
-            nrm += (double)part;
         }
     }
     if (norm_out) {
@@ -295,17 +294,16 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
             Cx<T> q[PER];
 #pragma unroll
             for (int u = 0; u < PER; ++u) q[u] = lds[tid + (uint32_t)u * NT];
-            T part = 0;  // the thread's PER squares in the state's precision
+            // the thread's PER squares, each exact in FP64, summed in FP64
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 Cx<T> o = q[u];
                 o.re *= s;
                 o.im *= s;
                 tile_store<!PERSIST>(psi + (base ^ a.uoff[u]), o);
-                part = fma(o.re, o.re, part);
-                part = fma(o.im, o.im, part);
+                nrm = fma((double)o.re, (double)o.re, nrm);
+                nrm = fma((double)o.im, (double)o.im, nrm);
             }
-            nrm += (double)part;
         }
         if (next) {
             __syncthreads();  // every thread has read the finished set
@@ -318,6 +316,65 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
         __syncthreads();  // the tile-set's LDS is reused for the partial sums
         nrm = block_sum<NT>(nrm, reinterpret_cast<double *>(lds_raw));
         if (tid == 0) norm_out[blockIdx.x] = nrm;
+    }
+}
+
+// ------------------------------------------------------------ relabelling
+
+// LDS slot of group coordinate s: the low four bits XORed with a fold of the
+// higher ones, so that sixteen lanes reading coordinates that differ in any
+// four high bits mostly hit distinct banks.
+__device__ __forceinline__ uint32_t perm_slot(uint32_t s) {
+    return s ^ (((s >> 4) ^ (s >> 8)) & 15u);
+}
+
+// One relabelling pass: every group of 2^12 elements (fixed bits outside
+// pos[]) is read with sixteen contiguous amplitudes per access, permuted
+// through LDS and written back in place, again sixteen contiguous
+// amplitudes per access.
+template <typename T>
+__global__ void __launch_bounds__(256) k_permute(Cx<T> *__restrict__ psi, PermArgs a) {
+    static_assert(kPermBits == 12, "256 threads x 16 slots per group");
+    __shared__ __align__(16) Cx<T> lds[1 << kPermBits];
+    const uint32_t t = threadIdx.x;
+    const uint64_t ngroups = 1ull << (a.n - kPermBits);
+    uint32_t it = 0;    // D^-1 of the thread's bits of the output coordinate
+    uint64_t toff = 0;  // the thread's bits (coordinates 0..7) as index bits
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if ((t >> j) & 1u) {
+            it ^= a.inv[j];
+            toff |= 1ull << a.pos[j];
+        }
+    }
+    for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        uint64_t base = g;
+#pragma unroll
+        for (int j = 0; j < kPermBits; ++j) base = insert_zero64(base, a.pos[j]);
+        base |= toff;
+        Cx<T> r[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            uint64_t uo = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if ((u >> j) & 1) uo |= 1ull << a.pos[8 + j];
+            r[u] = psi[base | uo];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lds[perm_slot(t + 256u * (uint32_t)u)] = r[u];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; ++u) r[u] = lds[perm_slot(it ^ a.ioff[u])];
+        __syncthreads();  // the group's LDS is reused by the next iteration
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            uint64_t uo = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if ((u >> j) & 1) uo |= 1ull << a.pos[8 + j];
+            psi[base | uo] = r[u];
+        }
     }
 }
 
@@ -472,6 +529,17 @@ static hipError_t plain_t(void *psi, const PlainArgs &a, hipStream_t s) {
 
 hipError_t launch_plain(prx_dtype dt, void *psi, const PlainArgs &a, hipStream_t s) {
     return dt == PRX_C64 ? plain_t<float>(psi, a, s) : plain_t<double>(psi, a, s);
+}
+
+unsigned permute_blocks(int n) { return capped_blocks(1ull << (n - kPermBits)); }
+
+hipError_t launch_permute(prx_dtype dt, void *psi, const PermArgs &a, hipStream_t s) {
+    const unsigned nb = permute_blocks(a.n);
+    if (dt == PRX_C64)
+        hipLaunchKernelGGL(k_permute<float>, dim3(nb), dim3(256), 0, s, (Cx<float> *)psi, a);
+    else
+        hipLaunchKernelGGL(k_permute<double>, dim3(nb), dim3(256), 0, s, (Cx<double> *)psi, a);
+    return hipGetLastError();
 }
 
 unsigned span_blocks(int n, int m) { return capped_blocks(((1ull << (n - m)) + 255u) / 256u); }

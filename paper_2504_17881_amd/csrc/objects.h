@@ -36,7 +36,7 @@ struct RotRecD {
     bool fold = false;  // device tau_a is -tau_a (static-sign variant with zeta_slot set)
 };
 
-enum PassKind { kPlain = 0, kSpan = 1, kTile = 2 };
+enum PassKind { kPlain = 0, kSpan = 1, kTile = 2, kPerm = 3 };
 
 struct Pass {
     int kind = kPlain;
@@ -53,6 +53,9 @@ struct Pass {
     size_t c0 = 0, c1 = 0;  // chunks
     double scale = 1.0;
     bool norm_out = false, renorm_in = false;
+    // relabelling (kPerm): index bit ppos[j] moves to index bit ppos[pdst[j]]
+    uint32_t ppos[kPermBits] = {};
+    uint8_t pdst[kPermBits] = {};
 };
 
 struct PlanCfg {
@@ -66,6 +69,7 @@ struct PlanCfg {
     bool span_only = false;  // batched plans: every pass is a span pass ...
     int pad_rank = 0;        // ... whose basis is padded to exactly this rank
     bool tile_only = false;  // batched plans: every pass is a tile pass
+    bool relabel = false;    // qubit-relabelling passes between segments
 };
 
 // Kernel arguments of a tile pass of a plan for n qubits.

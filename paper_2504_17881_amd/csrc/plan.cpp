@@ -605,6 +605,113 @@ void tile_args(int n, const Pass &ps, TileArgs &a) {
     a.scale = ps.scale;
 }
 
+// ------------------------------------------------------------ relabelling
+//
+// A layout places logical qubit q at index bit phys(q).  The planner only
+// uses layouts that exchange low bit j (j < 4) with one other bit ex[j]
+// (ex[j] = j: no exchange), so the low bits, whose 16 contiguous amplitudes
+// every tile pass keeps in its frame, can hold qubits the next rotations
+// act on.  Going from one such layout to another moves at most the 12 bits
+// {0..3} U ex_old U ex_new: one relabelling pass (kPerm).
+struct Layout {
+    uint32_t ex[4] = {0, 1, 2, 3};
+    bool identity() const { return ex[0] == 0 && ex[1] == 1 && ex[2] == 2 && ex[3] == 3; }
+    uint32_t phys(uint32_t q) const {
+        if (q < 4) return ex[q];
+        for (uint32_t j = 0; j < 4; ++j)
+            if (ex[j] == q) return j;
+        return q;
+    }
+    uint64_t map(uint64_t m) const {
+        uint64_t out = 0;
+        while (m) {
+            const uint32_t q = (uint32_t)__builtin_ctzll(m);
+            m &= m - 1;
+            out |= 1ull << phys(q);
+        }
+        return out;
+    }
+};
+
+// Passes the simple tile model needs for rotations [p, p + count) under a
+// layout: b low bits plus up to g virtual directions of the bits above.
+static size_t model_passes(const std::vector<KRot> &R, size_t p, size_t count, const Layout &L,
+                           int b, int g, int max_fuse, size_t *covered_by = nullptr,
+                           size_t pass_limit = ~(size_t)0) {
+    size_t passes = 0, j = p;
+    const size_t end = std::min(R.size(), p + count);
+    while (j < end && passes < pass_limit) {
+        Gf2 M;
+        size_t k = j;
+        for (; k < end && (int)(k - j) < max_fuse; ++k) {
+            const uint64_t xh = L.map(R[k].x) >> b;
+            if (xh == 0 || M.contains(xh)) continue;
+            if ((int)M.rank() < g) {
+                M.add(xh);
+                continue;
+            }
+            break;
+        }
+        j = k;
+        ++passes;
+    }
+    if (covered_by) *covered_by = j - p;
+    return passes;
+}
+
+// The layout that puts the four qubits most used by the X masks of
+// rotations [p, p + window) in the low bits (qubits already low stay).
+static Layout hot_layout(const std::vector<KRot> &R, size_t p, size_t window, int n) {
+    std::vector<int> cnt(n, 0);
+    const size_t end = std::min(R.size(), p + window);
+    for (size_t k = p; k < end; ++k)
+        for (uint64_t m = R[k].x; m; m &= m - 1) cnt[__builtin_ctzll(m)]++;
+    std::vector<uint32_t> q(n);
+    for (int i = 0; i < n; ++i) q[i] = (uint32_t)i;
+    std::stable_sort(q.begin(), q.end(), [&](uint32_t a, uint32_t b) { return cnt[a] > cnt[b]; });
+    bool want[64] = {};
+    for (int i = 0; i < 4; ++i) want[q[i]] = true;
+    Layout L;
+    // low qubits that stay; the others are exchanged with incoming ones
+    std::vector<uint32_t> in;
+    for (int i = 0; i < 4; ++i)
+        if (q[i] >= 4) in.push_back(q[i]);
+    size_t t = 0;
+    for (uint32_t j = 0; j < 4; ++j)
+        if (!want[j] && t < in.size()) L.ex[j] = in[t++];
+    return L;
+}
+
+// Relabelling pass from layout A to layout B (index bit phys_A(q) moves to
+// phys_B(q) for every qubit q).
+static Pass perm_pass(int n, const Layout &A, const Layout &B) {
+    std::vector<uint32_t> pos = {0, 1, 2, 3};
+    auto add = [&](uint32_t v) {
+        if (std::find(pos.begin(), pos.end(), v) == pos.end()) pos.push_back(v);
+    };
+    for (int j = 0; j < 4; ++j) {
+        add(A.ex[j]);
+        add(B.ex[j]);
+    }
+    for (uint32_t v = 4; pos.size() < (size_t)kPermBits && v < (uint32_t)n; ++v) add(v);
+    std::sort(pos.begin(), pos.end());
+    Pass ps;
+    ps.kind = kPerm;
+    for (int j = 0; j < kPermBits; ++j) ps.ppos[j] = pos[j];
+    // the qubit at index bit pos[j] under A
+    for (int j = 0; j < kPermBits; ++j) {
+        uint32_t q = pos[j];
+        if (q < 4)
+            q = A.ex[q] == q ? q : A.ex[q];  // logical qubit held at low bit j
+        else
+            for (uint32_t i = 0; i < 4; ++i)
+                if (A.ex[i] == pos[j]) q = i;
+        const uint32_t to = B.phys(q);
+        ps.pdst[j] = (uint8_t)(std::find(pos.begin(), pos.end(), to) - pos.begin());
+    }
+    return ps;
+}
+
 static void default_cfg(prx_dtype dt, PlanCfg &c) {
     c.B = (dt == PRX_C64) ? 12 : 11;
     c.m = 4;
@@ -625,6 +732,7 @@ static void apply_opts(const prx_plan_opts *o, PlanCfg &c) {
     if (o->renorm_every) c.renorm_every = o->renorm_every;
     if (o->commuting) c.commuting = o->commuting > 0;
     if (o->tile_only) c.tile_only = o->tile_only > 0;
+    if (o->relabel) c.relabel = o->relabel > 0;
 }
 
 template <typename T>
@@ -699,17 +807,81 @@ static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtyp
             for (int q = 0; q < pieces; ++q) P->rots.push_back(KRot{sched->x[j], sched->z[j], part, j});
         }
         P->end = P->rots.size();
-        Builder bld(*P, P->end);
-        // span passes need 2^(n - m) >= 1 cosets; tiny states fall back to plain
-        if (P->cfg.span_only)
-            bld.run_span_only();
-        else if (P->cfg.tile_only)
-            bld.run_tile_only();
-        else if (!fused || n < 4)
-            bld.run_plain();
-        else {
+        std::vector<RotRecD> recs;
+        const bool relabel = P->cfg.relabel && fused && !P->cfg.span_only &&
+                             n >= std::max(P->cfg.B + 2, 14) &&
+                             tile_supported(dtype, P->cfg.B, P->cfg.m);
+        if (!relabel) {
+            Builder bld(*P, P->end);
+            // span passes need 2^(n - m) >= 1 cosets; tiny states fall back to plain
+            if (P->cfg.span_only)
+                bld.run_span_only();
+            else if (P->cfg.tile_only)
+                bld.run_tile_only();
+            else if (!fused || n < 4)
+                bld.run_plain();
+            else {
+                if (P->cfg.span_m > n - 1) P->cfg.span_m = std::max(1, n - 1);
+                bld.run_fused();
+            }
+            recs.swap(bld.recs);
+        } else {
+            // Segments between relabelling passes.  At a pass boundary of
+            // the simple tile model the planner compares the passes needed
+            // for the next kRelabelHorizon passes' worth of rotations under
+            // the current layout and under the layout that brings the four
+            // qubits most used there into the low bits; it relabels when
+            // that saves at least kRelabelGain passes (a relabelling pass
+            // moves the state once, as a pass does, but runs no rotations).
             if (P->cfg.span_m > n - 1) P->cfg.span_m = std::max(1, n - 1);
-            bld.run_fused();
+            const int g = std::min(P->cfg.max_virtual, P->cfg.B - kMinTileLow);
+            const int b = P->cfg.B - g;
+            const int mf = P->cfg.max_fuse;
+            constexpr size_t kRelabelHorizon = 16, kRelabelGain = 3;
+            const std::vector<KRot> logical = P->rots;
+            // the layout worth switching to at rotation q, or `cur` itself
+            auto better = [&](size_t q, const Layout &cur) {
+                size_t cov = 0;
+                model_passes(logical, q, P->end - q, cur, b, g, mf, &cov, kRelabelHorizon);
+                const size_t hz = std::max<size_t>(cov, 1);
+                const Layout hot = hot_layout(logical, q, hz, n);
+                if (std::memcmp(hot.ex, cur.ex, sizeof(cur.ex)) == 0) return cur;
+                const size_t a = model_passes(logical, q, hz, cur, b, g, mf);
+                const size_t h = model_passes(logical, q, hz, hot, b, g, mf);
+                return a >= h + kRelabelGain ? hot : cur;
+            };
+            Layout cur;
+            size_t p = 0;
+            while (p < P->end) {
+                const Layout use = better(p, cur);
+                if (std::memcmp(use.ex, cur.ex, sizeof(cur.ex)) != 0) {
+                    P->passes.push_back(perm_pass(n, cur, use));
+                    cur = use;
+                }
+                // the segment runs to the next model pass boundary at which
+                // relabelling pays
+                size_t q = p;
+                for (;;) {
+                    size_t c1 = 0;
+                    model_passes(logical, q, P->end - q, cur, b, g, mf, &c1, 1);
+                    q += std::max<size_t>(c1, 1);
+                    if (q >= P->end) break;
+                    const Layout nx = better(q, cur);
+                    if (std::memcmp(nx.ex, cur.ex, sizeof(cur.ex)) != 0) break;
+                }
+                const size_t seg_end = std::min(q, P->end);
+                for (size_t k = p; k < seg_end; ++k) {
+                    P->rots[k].x = cur.map(logical[k].x);
+                    P->rots[k].z = cur.map(logical[k].z);
+                }
+                P->begin = p;
+                Builder bld(*P, seg_end);
+                bld.run_fused();
+                recs.insert(recs.end(), bld.recs.begin(), bld.recs.end());
+                p = seg_end;
+            }
+            P->begin = 0;
+            if (!cur.identity()) P->passes.push_back(perm_pass(n, cur, Layout{}));
         }
         // renormalisation between consecutive fused passes
         if (dtype == PRX_C64 && P->cfg.renorm_every > 0) {
@@ -717,18 +889,18 @@ static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtyp
             for (size_t i = 0; i + 1 < P->passes.size(); ++i) {
                 Pass &a = P->passes[i];
                 Pass &b = P->passes[i + 1];
-                if (a.kind == kPlain) continue;
+                if (a.kind == kPlain || a.kind == kPerm) continue;
                 ++f;
-                if (b.kind != kPlain && f % P->cfg.renorm_every == 0) {
+                if ((b.kind == kSpan || b.kind == kTile) && f % P->cfg.renorm_every == 0) {
                     a.norm_out = true;
                     b.renorm_in = true;
                 }
             }
         }
         if (dtype == PRX_C64)
-            pack_records<float>(*P, bld.recs);
+            pack_records<float>(*P, recs);
         else
-            pack_records<double>(*P, bld.recs);
+            pack_records<double>(*P, recs);
         // workspace layout
         size_t maxblocks = 1;
         for (const Pass &ps : P->passes) {
@@ -787,6 +959,8 @@ prx_status prx_plan_get_info(const prx_plan *P, prx_plan_info *o) {
     o->plain_passes = P->plain_passes;
     o->span_passes = P->span_passes;
     o->tile_passes = P->tile_passes;
+    o->relabel_passes = 0;
+    for (const Pass &ps : P->passes) o->relabel_passes += ps.kind == kPerm;
     o->workspace_bytes = P->ws.total;
     o->mean_fuse = P->passes.empty() ? 0.0 : (double)P->rots.size() / (double)P->passes.size();
     o->tile_qubits = P->cfg.B;
@@ -839,6 +1013,23 @@ static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws
         if (ev) PRX_HIP(hipEventRecord(ev[3 * i], s));
         if (ps.kind == kPlain) {
             e = launch_plain(P->dtype, psi, plain_args(P->n, P->rots[ps.r0]), s);
+        } else if (ps.kind == kPerm) {
+            PermArgs a;
+            std::memset(&a, 0, sizeof(a));
+            uint32_t dinv[kPermBits];
+            for (int j = 0; j < kPermBits; ++j) {
+                a.pos[j] = ps.ppos[j];
+                dinv[ps.pdst[j]] = (uint32_t)j;
+            }
+            for (int j = 0; j < kPermBits; ++j) a.inv[j] = (uint16_t)(1u << dinv[j]);
+            for (int u = 0; u < 16; ++u) {
+                uint32_t v = 0;
+                for (int j = 0; j < 4; ++j)
+                    if ((u >> j) & 1) v ^= a.inv[8 + j];
+                a.ioff[u] = (uint16_t)v;
+            }
+            a.n = P->n;
+            e = launch_permute(P->dtype, psi, a, s);
         } else if (ps.kind == kSpan) {
             SpanArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -935,8 +1126,15 @@ prx_status prx_plan_pass(const prx_plan *P, size_t i, prx_pass_info *o) {
     for (int k = 0; k < kMaxChunkRank; ++k) o->fscale[k] = ps.fscale[k];
     o->norm_out = ps.norm_out;
     o->renorm_in = ps.renorm_in;
+    for (int k = 0; k < kPermBits; ++k) {
+        o->perm_pos[k] = ps.ppos[k];
+        o->perm_dst[k] = ps.pdst[k];
+    }
     if (ps.kind == kPlain) {
         o->grid_blocks = plain_blocks(P->n, P->rots[ps.r0].x == 0);
+        o->block_threads = 256;
+    } else if (ps.kind == kPerm) {
+        o->grid_blocks = permute_blocks(P->n);
         o->block_threads = 256;
     } else if (ps.kind == kSpan) {
         o->grid_blocks = span_blocks(P->n, ps.m);

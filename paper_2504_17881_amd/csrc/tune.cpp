@@ -39,11 +39,12 @@ void tune_store(int n, prx_dtype dt, const prx_plan_opts &o) {
 }
 
 static const char *kFields[] = {"tile_qubits", "chunk_rank", "max_fuse", "span_max",
-                                "max_virtual", "renorm_every", "commuting"};
+                                "max_virtual", "renorm_every", "commuting", "relabel"};
+static constexpr int kNumFields = (int)(sizeof(kFields) / sizeof(kFields[0]));
 
 static int *field(prx_plan_opts &o, int i) {
     int *f[] = {&o.tile_qubits, &o.chunk_rank, &o.max_fuse, &o.span_max,
-                &o.max_virtual, &o.renorm_every, &o.commuting};
+                &o.max_virtual, &o.renorm_every, &o.commuting, &o.relabel};
     return f[i];
 }
 
@@ -110,6 +111,14 @@ prx_status prx_autotune_progress(void *psi, int n, prx_dtype dtype, const prx_sc
         prx_plan *P = nullptr;
         prx_status st = prx_plan_create(sched, n, dtype, 0, sched->x.size(), PRX_FUSED, &o, &P);
         if (st != PRX_OK) return PRX_OK;  // setting not applicable: skip
+        if (o.relabel) {  // same plan as without relabelling: nothing to time
+            bool any = false;
+            for (const Pass &ps : P->passes) any |= ps.kind == kPerm;
+            if (!any) {
+                prx_plan_destroy(P);
+                return PRX_OK;
+            }
+        }
         float ms = 0.f;
         if (P->ws.total <= ws_bytes) {
             st = time_plan(P, psi, ws, ws_bytes, s, &ms);
@@ -181,6 +190,13 @@ prx_status prx_autotune_progress(void *psi, int n, prx_dtype dtype, const prx_sc
             o.commuting = 1;
             PRX_TUNE_RUN(o);
         }
+        // Stage 4: the best setting with qubit relabelling allowed (timed
+        // only when the planner inserts relabelling passes)
+        {
+            prx_plan_opts o = best;
+            o.relabel = 1;
+            PRX_TUNE_RUN(o);
+        }
     }
 #undef PRX_TUNE_RUN
     if (trials == 0) return fail(PRX_ERR_INVALID, "workspace too small for every candidate");
@@ -206,7 +222,7 @@ prx_status prx_autotune_save(const char *path) {
         for (auto &kv : g_cache) {
             os << (first ? "\n" : ",\n") << "  \"" << kv.first << "\": {";
             prx_plan_opts o = kv.second;
-            for (int i = 0; i < 7; ++i) os << (i ? ", " : "") << "\"" << kFields[i] << "\": " << *field(o, i);
+            for (int i = 0; i < kNumFields; ++i) os << (i ? ", " : "") << "\"" << kFields[i] << "\": " << *field(o, i);
             os << "}";
             first = false;
         }
@@ -240,7 +256,7 @@ prx_status prx_autotune_load(const char *path) {
         const std::string body = t.substr(b0, b1 - b0);
         prx_plan_opts o;
         std::memset(&o, 0, sizeof(o));
-        for (int i = 0; i < 7; ++i) {
+        for (int i = 0; i < kNumFields; ++i) {
             const std::string fk = std::string("\"") + kFields[i] + "\"";
             const size_t p = body.find(fk);
             if (p == std::string::npos) continue;

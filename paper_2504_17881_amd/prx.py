@@ -64,7 +64,8 @@ class prx_plan_opts(ctypes.Structure):
     _fields_ = [("tile_qubits", ctypes.c_int), ("chunk_rank", ctypes.c_int),
                 ("max_fuse", ctypes.c_int), ("span_max", ctypes.c_int),
                 ("max_virtual", ctypes.c_int), ("renorm_every", ctypes.c_int),
-                ("commuting", ctypes.c_int), ("tile_only", ctypes.c_int)]
+                ("commuting", ctypes.c_int), ("tile_only", ctypes.c_int),
+                ("relabel", ctypes.c_int)]
 
 
 class prx_plan_info(ctypes.Structure):
@@ -72,7 +73,8 @@ class prx_plan_info(ctypes.Structure):
                 ("plain_passes", _sz), ("span_passes", _sz), ("tile_passes", _sz),
                 ("workspace_bytes", _sz), ("mean_fuse", ctypes.c_double),
                 ("tile_qubits", ctypes.c_int), ("chunk_rank", ctypes.c_int),
-                ("n", ctypes.c_int), ("dtype", ctypes.c_int)]
+                ("n", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("relabel_passes", _sz)]
 
 
 class prx_pass_info(ctypes.Structure):
@@ -84,7 +86,8 @@ class prx_pass_info(ctypes.Structure):
                 ("vmask", ctypes.c_uint64 * 10), ("tpivot", ctypes.c_uint32 * 10),
                 ("scale", ctypes.c_double), ("fscale", ctypes.c_double * 6),
                 ("norm_out", ctypes.c_int), ("renorm_in", ctypes.c_int),
-                ("grid_blocks", ctypes.c_uint), ("block_threads", ctypes.c_uint)]
+                ("grid_blocks", ctypes.c_uint), ("block_threads", ctypes.c_uint),
+                ("perm_pos", ctypes.c_uint32 * 12), ("perm_dst", ctypes.c_uint32 * 12)]
 
 
 class prx_chunk_info(ctypes.Structure):
@@ -404,7 +407,7 @@ def prx_plan_pass(plan: int, i: int) -> dict:
     o = prx_pass_info()
     _check(_lib.prx_plan_pass(plan, i, ctypes.byref(o)))
     d = {f: getattr(o, f) for f, _ in prx_pass_info._fields_}
-    for k in ("basis", "pivot", "vmask", "tpivot", "fscale"):
+    for k in ("basis", "pivot", "vmask", "tpivot", "fscale", "perm_pos", "perm_dst"):
         d[k] = list(d[k])
     return d
 

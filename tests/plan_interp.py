@@ -112,6 +112,22 @@ def run_plan(plan: int, psi0: np.ndarray, n: int) -> np.ndarray:
         if ps["renorm_in"]:
             assert pending is not None
             scale *= pending
+        if ps["kind"] == 3:
+            # relabelling: index bit pos[j] of every amplitude moves to pos[dst[j]]
+            assert ps["rot_count"] == 0
+            pos, dst = ps["perm_pos"], ps["perm_dst"]
+            assert sorted(dst) == list(range(12)) and pos == sorted(pos) and pos[:4] == [0, 1, 2, 3]
+            k = np.arange(1 << n, dtype=np.uint64)
+            kn = k.copy()
+            for j in range(12):
+                kn &= ~(np.uint64(1) << np.uint64(pos[j]))
+            for j in range(12):
+                bit = (k >> np.uint64(pos[j])) & np.uint64(1)
+                kn |= bit << np.uint64(pos[dst[j]])
+            out = np.empty_like(psi)
+            out[kn.astype(np.int64)] = psi
+            psi = out
+            continue
         if ps["kind"] == 0:
             assert len(recs) == 1
             psi = _plain(psi, n, recs[0])

@@ -267,3 +267,88 @@ def test_random_workload_exercises_every_rank4_variant():
     assert sorted(used) == list(range(64))
     P.prx_plan_destroy(pl)
     P.prx_sched_destroy(s)
+
+
+def _skewed_rotations(n, M, seed, hot, extra):
+    """Rotations whose X masks hold two qubits of `hot` and `extra` random
+    qubits above the low four: a qubit usage that the low index bits of the
+    given order do not serve."""
+    rng = np.random.default_rng(seed)
+    x = np.zeros(M, dtype=np.uint64)
+    z = rng.integers(0, 1 << n, size=M, dtype=np.uint64)
+    for i in range(M):
+        m = 0
+        for q in rng.choice(hot, size=2, replace=False):
+            m |= 1 << int(q)
+        for _ in range(extra):
+            m |= 1 << int(rng.integers(4, n))
+        x[i] = m
+    return x, z, rng.uniform(-0.3, 0.3, size=M)
+
+
+def _layouts_of(plan, n):
+    """The bit order in force at every kernel rotation: index bit of each
+    qubit, following the plan's relabelling passes."""
+    info = P.prx_plan_get_info(plan)
+    phys = list(range(n))  # phys[q] = index bit of qubit q
+    at = {}
+    for pi in range(info["passes"]):
+        ps = P.prx_plan_pass(plan, pi)
+        if ps["kind"] == 3:
+            pos, dst = ps["perm_pos"], ps["perm_dst"]
+            move = {pos[j]: pos[dst[j]] for j in range(12)}
+            phys = [move.get(b, b) for b in phys]
+            continue
+        for r in range(ps["rot_begin"], ps["rot_begin"] + ps["rot_count"]):
+            at[r] = list(phys)
+    return at, phys
+
+
+def _map(mask, phys):
+    return sum(1 << phys[q] for q in range(len(phys)) if (int(mask) >> q) & 1)
+
+
+@pytest.mark.parametrize("dtype,B,G", [(P.PRX_C128, 11, 7), (P.PRX_C64, 12, 8)])
+def test_relabelled_plans_match_oracle(dtype, B, G):
+    """Relabelling passes (kind 3) move the qubits the next rotations use into
+    the low index bits.  Two phases with different hot qubits need a
+    relabelling, a layout-to-layout relabelling and the final restore; the
+    interpreter, which applies the exported bit moves, reproduces the
+    oracle, every kernel rotation carries the schedule's masks in the bit
+    order in force, and the plan ends in the original order with fewer
+    passes than without relabelling."""
+    n = 17
+    x1, z1, p1 = _skewed_rotations(n, 500, 6, [11, 12, 14, 15], 2)
+    x2, z2, p2 = _skewed_rotations(n, 500, 7, [5, 7, 13, 16], 2)
+    x, z, phi = (np.concatenate([x1, x2]), np.concatenate([z1, z2]), np.concatenate([p1, p2]))
+    s = _sched(n, x, z, phi)
+    psi0 = synth.gaussian_state(n, 1)
+    ref = sv.c_apply_rotations(psi0, x, z, phi)
+    plain = P.prx_plan_create(s, n, dtype, 0, len(x), P.PRX_FUSED,
+                              dict(tile_qubits=B, max_virtual=G))
+    base = P.prx_plan_get_info(plain)["passes"]
+    P.prx_plan_destroy(plain)
+    pl = P.prx_plan_create(s, n, dtype, 0, len(x), P.PRX_FUSED,
+                           dict(tile_qubits=B, max_virtual=G, relabel=1))
+    info = P.prx_plan_get_info(pl)
+    assert info["relabel_passes"] >= 3 and info["passes"] < base
+    at, final = _layouts_of(pl, n)
+    assert final == list(range(n))
+    for i in range(info["kernel_rotations"]):
+        r = P.prx_plan_rotation(pl, i)
+        assert r["x"] == _map(x[r["source"]], at[i]) and r["z"] == _map(z[r["source"]], at[i])
+    out = run_plan(pl, psi0, n)
+    tol = 1e-12 if dtype == P.PRX_C128 else 8 * 2.0 ** -24 * math.sqrt(len(x))
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= tol
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+
+
+def test_relabel_is_ignored_on_small_states_and_uniform_usage():
+    n = 12
+    x, z, phi = synth.random_pauli_rotations(n, 200, seed=3)
+    s = _sched(n, x, z, phi)
+    pl = P.prx_plan_create(s, n, P.PRX_C64, 0, 200, P.PRX_FUSED, dict(relabel=1))
+    assert P.prx_plan_get_info(pl)["relabel_passes"] == 0
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
