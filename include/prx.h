@@ -161,6 +161,8 @@ typedef struct {
                             bits, which every tile pass keeps in its frame; the last pass
                             restores the original order (default 0; needs n >= 14 and
                             n >= tile_qubits + 2, otherwise ignored) */
+    int max_grid;        /* workgroups per sweep launch, at most 2^22 (the default); the
+                            kernels stride over the remaining cosets or tile-sets */
 } prx_plan_opts;
 
 /* Summary of a plan. */

@@ -164,17 +164,21 @@ prx_status plan_create_cfg(const prx_sched *sched, int n, prx_dtype dtype, const
 
 // ------------------------------------------------------------ launchers
 // All enqueue on `stream` and return hipGetLastError() of the launch.
-hipError_t launch_plain(prx_dtype dt, void *psi, const PlainArgs &a, hipStream_t s);
+// `cap` limits the workgroups of a launch (at most kMaxGridBlocks); the
+// kernels stride over the rest.
+hipError_t launch_plain(prx_dtype dt, void *psi, const PlainArgs &a, hipStream_t s,
+                        unsigned cap);
 hipError_t launch_span(prx_dtype dt, int m, void *psi, const SpanArgs &a, const void *rots,
                        const double *renorm_in, double *norm_out, hipStream_t s,
-                       unsigned *blocks_out);
+                       unsigned *blocks_out, unsigned cap);
 hipError_t launch_tile(prx_dtype dt, int B, int m, void *psi, const TileArgs &a,
                        const void *rots, const ChunkRec *chunks, const double *renorm_in,
-                       double *norm_out, hipStream_t s, unsigned *blocks_out);
+                       double *norm_out, hipStream_t s, unsigned *blocks_out, unsigned cap);
 // Qubit relabelling: one pass over the state, in place (every 2^12-element
 // group is closed under the permutation).
-hipError_t launch_permute(prx_dtype dt, void *psi, const PermArgs &a, hipStream_t s);
-unsigned permute_blocks(int n);
+hipError_t launch_permute(prx_dtype dt, void *psi, const PermArgs &a, hipStream_t s,
+                          unsigned cap);
+unsigned permute_blocks(int n, unsigned cap);
 // partial sums -> 1/sqrt(sum) into scale_out[0]; scale_out[1 .. kRenormStage]
 // is stage-1 scratch (two fixed-shape kernels, deterministic)
 static constexpr unsigned kRenormStage = 128;
@@ -184,9 +188,9 @@ hipError_t launch_renorm_finish(const double *partials, unsigned count, double *
 // work-items, inside a dispatch's 32-bit work-item range); the kernels
 // stride over the rest.
 static constexpr uint64_t kMaxGridBlocks = 1ull << 22;
-unsigned span_blocks(int n, int m);
-unsigned tile_blocks(int n, int B);
-unsigned plain_blocks(int n, bool diag);
+unsigned span_blocks(int n, int m, unsigned cap);
+unsigned tile_blocks(int n, int B, unsigned cap);
+unsigned plain_blocks(int n, bool diag, unsigned cap);
 bool span_supported(prx_dtype dt, int m);
 bool tile_supported(prx_dtype dt, int B, int m);
 

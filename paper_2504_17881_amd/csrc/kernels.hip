@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
     // behind the stores in the same iteration, and the stores drain while
     // the next set is computed.
     Cx<T> r[PER];
-    if (w < nsets) {
+    if (PERSIST && w < nsets) {
         const uint64_t b0 = base_of(tile_of(w));
 #pragma unroll
         for (int u = 0; u < PER; ++u) r[u] = tile_load<!PERSIST>(psi + (b0 ^ a.uoff[u]));
@@ -280,6 +280,16 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
     for (; w < nsets; w += gridDim.x) {
         const uint64_t tb = tile_of(w);
         const uint64_t base = base_of(tb);
+        if (!PERSIST) {
+            // one set per iteration (several when the grid is capped): every
+            // thread has stored the previous set before it is overwritten
+            if (w >= gridDim.x) __syncthreads();
+#pragma unroll
+            for (int u = 0; u < PER; ++u) r[u] = tile_load<!PERSIST>(psi + (base ^ a.uoff[u]));
+#pragma unroll
+            for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
+            __syncthreads();
+        }
         const uint32_t wn = w + gridDim.x;
         const bool next = PERSIST && wn < nsets;
         if (next) {
@@ -506,35 +516,36 @@ __global__ void __launch_bounds__(256) k_scale(Cx<T> *__restrict__ a, uint64_t N
 // ------------------------------------------------------------- launchers
 
 static unsigned ceil_div_u(uint64_t a, uint64_t b) { return (unsigned)((a + b - 1) / b); }
-static unsigned capped_blocks(uint64_t want) {
-    return (unsigned)std::min<uint64_t>(want ? want : 1, kMaxGridBlocks);
+static unsigned capped_blocks(uint64_t want, unsigned cap) {
+    const uint64_t c = std::max<uint64_t>(1, std::min<uint64_t>(cap, kMaxGridBlocks));
+    return (unsigned)std::min<uint64_t>(want ? want : 1, c);
 }
 
 template <typename T>
-static hipError_t plain_t(void *psi, const PlainArgs &a, hipStream_t s) {
+static hipError_t plain_t(void *psi, const PlainArgs &a, hipStream_t s, unsigned cap) {
     constexpr int U = 4;
     if (a.x == 0) {
         const uint64_t N = 1ull << a.n;
-        hipLaunchKernelGGL((k_plain_diag<T, U>), dim3(capped_blocks((N + 256u * U - 1) / (256u * U))),
+        hipLaunchKernelGGL((k_plain_diag<T, U>), dim3(capped_blocks((N + 256u * U - 1) / (256u * U), cap)),
                            dim3(256), 0, s,
                            (Cx<T> *)psi, a, N);
     } else {
         const uint64_t np = 1ull << (a.n - 1);
-        hipLaunchKernelGGL((k_plain_pair<T, U>), dim3(capped_blocks((np + 256u * U - 1) / (256u * U))),
+        hipLaunchKernelGGL((k_plain_pair<T, U>), dim3(capped_blocks((np + 256u * U - 1) / (256u * U), cap)),
                            dim3(256), 0, s,
                            (Cx<T> *)psi, a, np);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_plain(prx_dtype dt, void *psi, const PlainArgs &a, hipStream_t s) {
-    return dt == PRX_C64 ? plain_t<float>(psi, a, s) : plain_t<double>(psi, a, s);
+hipError_t launch_plain(prx_dtype dt, void *psi, const PlainArgs &a, hipStream_t s, unsigned cap) {
+    return dt == PRX_C64 ? plain_t<float>(psi, a, s, cap) : plain_t<double>(psi, a, s, cap);
 }
 
-unsigned permute_blocks(int n) { return capped_blocks(1ull << (n - kPermBits)); }
+unsigned permute_blocks(int n, unsigned cap) { return capped_blocks(1ull << (n - kPermBits), cap); }
 
-hipError_t launch_permute(prx_dtype dt, void *psi, const PermArgs &a, hipStream_t s) {
-    const unsigned nb = permute_blocks(a.n);
+hipError_t launch_permute(prx_dtype dt, void *psi, const PermArgs &a, hipStream_t s, unsigned cap) {
+    const unsigned nb = permute_blocks(a.n, cap);
     if (dt == PRX_C64)
         hipLaunchKernelGGL(k_permute<float>, dim3(nb), dim3(256), 0, s, (Cx<float> *)psi, a);
     else
@@ -542,16 +553,18 @@ hipError_t launch_permute(prx_dtype dt, void *psi, const PermArgs &a, hipStream_
     return hipGetLastError();
 }
 
-unsigned span_blocks(int n, int m) { return capped_blocks(((1ull << (n - m)) + 255u) / 256u); }
-unsigned tile_blocks(int n, int B) { return capped_blocks(1ull << (n - B)); }
-unsigned plain_blocks(int n, bool diag) {
+unsigned span_blocks(int n, int m, unsigned cap) {
+    return capped_blocks(((1ull << (n - m)) + 255u) / 256u, cap);
+}
+unsigned tile_blocks(int n, int B, unsigned cap) { return capped_blocks(1ull << (n - B), cap); }
+unsigned plain_blocks(int n, bool diag, unsigned cap) {
     const uint64_t items = diag ? (1ull << n) : (1ull << (n - 1));
-    return capped_blocks((items + 1023u) / 1024u);
+    return capped_blocks((items + 1023u) / 1024u, cap);
 }
 
 // Persistent tile kernels stride over the 2^(n-B) tile-sets with the
 // workgroups that fit on the device at once (cached per device and kernel).
-static unsigned tile_grid(const void *kernel, int n, int B, int threads) {
+static unsigned tile_grid(const void *kernel, int n, int B, int threads, unsigned cap) {
     struct Entry {
         const void *k;
         int dev;
@@ -571,11 +584,11 @@ static unsigned tile_grid(const void *kernel, int n, int B, int threads) {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
             cus <= 0 || per <= 0)
-            return tile_blocks(n, B);  // one workgroup per tile-set
+            return tile_blocks(n, B, cap);  // one workgroup per tile-set
         resident = (unsigned)(cus * per);
         if (used < 64) cache[used++] = Entry{kernel, dev, resident};
     }
-    const unsigned sets = tile_blocks(n, B);
+    const unsigned sets = tile_blocks(n, B, cap);
     return sets < resident ? sets : resident;
 }
 
@@ -583,8 +596,9 @@ bool span_supported(prx_dtype, int m) { return m >= 1 && m <= 5; }
 
 template <typename T>
 static hipError_t span_t(int m, void *psi, const SpanArgs &a, const void *rots,
-                         const double *rin, double *nout, hipStream_t s, unsigned *blocks) {
-    const unsigned nb = span_blocks(a.n, m);
+                         const double *rin, double *nout, hipStream_t s, unsigned *blocks,
+                         unsigned cap) {
+    const unsigned nb = span_blocks(a.n, m, cap);
     *blocks = nb;
     const RotRec<T> *r = (const RotRec<T> *)rots;
     Cx<T> *p = (Cx<T> *)psi;
@@ -601,9 +615,9 @@ static hipError_t span_t(int m, void *psi, const SpanArgs &a, const void *rots,
 
 hipError_t launch_span(prx_dtype dt, int m, void *psi, const SpanArgs &a, const void *rots,
                        const double *renorm_in, double *norm_out, hipStream_t s,
-                       unsigned *blocks_out) {
-    return dt == PRX_C64 ? span_t<float>(m, psi, a, rots, renorm_in, norm_out, s, blocks_out)
-                         : span_t<double>(m, psi, a, rots, renorm_in, norm_out, s, blocks_out);
+                       unsigned *blocks_out, unsigned cap) {
+    return dt == PRX_C64 ? span_t<float>(m, psi, a, rots, renorm_in, norm_out, s, blocks_out, cap)
+                         : span_t<double>(m, psi, a, rots, renorm_in, norm_out, s, blocks_out, cap);
 }
 
 // (B, M) pairs instantiated for the tile kernel.
@@ -619,10 +633,10 @@ bool tile_supported(prx_dtype dt, int B, int m) {
 template <typename T, int B, int M>
 static hipError_t tile_launch_one(void *psi, const TileArgs &a, const void *rots,
                                   const ChunkRec *chunks, const double *rin, double *nout,
-                                  hipStream_t s, unsigned *blocks) {
+                                  hipStream_t s, unsigned *blocks, unsigned cap) {
     const unsigned nb = TilePersist<T, B>::value
-                            ? tile_grid((const void *)k_tile<T, B, M>, a.n, B, 1 << (B - M))
-                            : tile_blocks(a.n, B);
+                            ? tile_grid((const void *)k_tile<T, B, M>, a.n, B, 1 << (B - M), cap)
+                            : tile_blocks(a.n, B, cap);
     *blocks = nb;
     hipLaunchKernelGGL((k_tile<T, B, M>), dim3(nb), dim3(1 << (B - M)), 0, s, (Cx<T> *)psi, a,
                        (const RotRec<T> *)rots, chunks, rin, nout);
@@ -632,11 +646,11 @@ static hipError_t tile_launch_one(void *psi, const TileArgs &a, const void *rots
 template <typename T>
 static hipError_t tile_t(int B, int m, void *psi, const TileArgs &a, const void *rots,
                          const ChunkRec *chunks, const double *rin, double *nout, hipStream_t s,
-                         unsigned *blocks) {
-#define PRX_TL(BB, MM)                                                                    \
-    if (B == BB && m == MM) {                                                             \
-        if constexpr (sizeof(T) == 4 || BB <= 12)                                         \
-            return tile_launch_one<T, BB, MM>(psi, a, rots, chunks, rin, nout, s, blocks); \
+                         unsigned *blocks, unsigned cap) {
+#define PRX_TL(BB, MM)                                                                         \
+    if (B == BB && m == MM) {                                                                  \
+        if constexpr (sizeof(T) == 4 || BB <= 12)                                              \
+            return tile_launch_one<T, BB, MM>(psi, a, rots, chunks, rin, nout, s, blocks, cap); \
         return hipErrorInvalidValue;                                                      \
     }
     PRX_TILE_SHAPES(PRX_TL)
@@ -646,10 +660,10 @@ static hipError_t tile_t(int B, int m, void *psi, const TileArgs &a, const void 
 
 hipError_t launch_tile(prx_dtype dt, int B, int m, void *psi, const TileArgs &a,
                        const void *rots, const ChunkRec *chunks, const double *renorm_in,
-                       double *norm_out, hipStream_t s, unsigned *blocks_out) {
+                       double *norm_out, hipStream_t s, unsigned *blocks_out, unsigned cap) {
     return dt == PRX_C64
-               ? tile_t<float>(B, m, psi, a, rots, chunks, renorm_in, norm_out, s, blocks_out)
-               : tile_t<double>(B, m, psi, a, rots, chunks, renorm_in, norm_out, s, blocks_out);
+               ? tile_t<float>(B, m, psi, a, rots, chunks, renorm_in, norm_out, s, blocks_out, cap)
+               : tile_t<double>(B, m, psi, a, rots, chunks, renorm_in, norm_out, s, blocks_out, cap);
 }
 
 hipError_t launch_renorm_finish(const double *partials, unsigned count, double *scale_out,

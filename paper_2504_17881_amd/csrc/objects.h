@@ -70,6 +70,7 @@ struct PlanCfg {
     int pad_rank = 0;        // ... whose basis is padded to exactly this rank
     bool tile_only = false;  // batched plans: every pass is a tile pass
     bool relabel = false;    // qubit-relabelling passes between segments
+    unsigned grid_cap = (unsigned)kMaxGridBlocks;  // workgroups per sweep launch
 };
 
 // Kernel arguments of a tile pass of a plan for n qubits.

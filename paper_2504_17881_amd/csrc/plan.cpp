@@ -733,6 +733,8 @@ static void apply_opts(const prx_plan_opts *o, PlanCfg &c) {
     if (o->commuting) c.commuting = o->commuting > 0;
     if (o->tile_only) c.tile_only = o->tile_only > 0;
     if (o->relabel) c.relabel = o->relabel > 0;
+    if (o->max_grid > 0)
+        c.grid_cap = (unsigned)std::min<uint64_t>((uint64_t)o->max_grid, kMaxGridBlocks);
 }
 
 template <typename T>
@@ -905,7 +907,8 @@ static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtyp
         size_t maxblocks = 1;
         for (const Pass &ps : P->passes) {
             if (!ps.norm_out) continue;
-            const size_t nb = ps.kind == kSpan ? span_blocks(n, ps.m) : tile_blocks(n, ps.B);
+            const size_t nb = ps.kind == kSpan ? span_blocks(n, ps.m, P->cfg.grid_cap)
+                                               : tile_blocks(n, ps.B, P->cfg.grid_cap);
             maxblocks = std::max(maxblocks, nb);
         }
         WsLayout &w = P->ws;
@@ -1012,7 +1015,7 @@ static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws
         hipError_t e = hipSuccess;
         if (ev) PRX_HIP(hipEventRecord(ev[3 * i], s));
         if (ps.kind == kPlain) {
-            e = launch_plain(P->dtype, psi, plain_args(P->n, P->rots[ps.r0]), s);
+            e = launch_plain(P->dtype, psi, plain_args(P->n, P->rots[ps.r0]), s, P->cfg.grid_cap);
         } else if (ps.kind == kPerm) {
             PermArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -1029,7 +1032,7 @@ static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws
                 a.ioff[u] = (uint16_t)v;
             }
             a.n = P->n;
-            e = launch_permute(P->dtype, psi, a, s);
+            e = launch_permute(P->dtype, psi, a, s, P->cfg.grid_cap);
         } else if (ps.kind == kSpan) {
             SpanArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -1042,11 +1045,12 @@ static prx_status execute_impl(const prx_plan *P, void *psi, void *ws, size_t ws
             a.n = P->n;
             a.scale = ps.scale;
             for (int k = 0; k < kMaxChunkRank; ++k) a.fscale[k] = ps.fscale[k];
-            e = launch_span(P->dtype, ps.m, psi, a, rots, rin, nout, s, &blocks);
+            e = launch_span(P->dtype, ps.m, psi, a, rots, rin, nout, s, &blocks, P->cfg.grid_cap);
         } else {
             TileArgs a;
             tile_args(P->n, ps, a);
-            e = launch_tile(P->dtype, ps.B, ps.m, psi, a, rots, chunks, rin, nout, s, &blocks);
+            e = launch_tile(P->dtype, ps.B, ps.m, psi, a, rots, chunks, rin, nout, s, &blocks,
+                            P->cfg.grid_cap);
         }
         if (e != hipSuccess) return hip_fail(e, "pass launch");
         if (ev) PRX_HIP(hipEventRecord(ev[3 * i + 1], s));
@@ -1131,16 +1135,16 @@ prx_status prx_plan_pass(const prx_plan *P, size_t i, prx_pass_info *o) {
         o->perm_dst[k] = ps.pdst[k];
     }
     if (ps.kind == kPlain) {
-        o->grid_blocks = plain_blocks(P->n, P->rots[ps.r0].x == 0);
+        o->grid_blocks = plain_blocks(P->n, P->rots[ps.r0].x == 0, P->cfg.grid_cap);
         o->block_threads = 256;
     } else if (ps.kind == kPerm) {
-        o->grid_blocks = permute_blocks(P->n);
+        o->grid_blocks = permute_blocks(P->n, P->cfg.grid_cap);
         o->block_threads = 256;
     } else if (ps.kind == kSpan) {
-        o->grid_blocks = span_blocks(P->n, ps.m);
+        o->grid_blocks = span_blocks(P->n, ps.m, P->cfg.grid_cap);
         o->block_threads = 256;
     } else {
-        o->grid_blocks = tile_blocks(P->n, ps.B);
+        o->grid_blocks = tile_blocks(P->n, ps.B, P->cfg.grid_cap);
         o->block_threads = 1u << (ps.B - ps.m);
     }
     return PRX_OK;

@@ -65,7 +65,7 @@ class prx_plan_opts(ctypes.Structure):
                 ("max_fuse", ctypes.c_int), ("span_max", ctypes.c_int),
                 ("max_virtual", ctypes.c_int), ("renorm_every", ctypes.c_int),
                 ("commuting", ctypes.c_int), ("tile_only", ctypes.c_int),
-                ("relabel", ctypes.c_int)]
+                ("relabel", ctypes.c_int), ("max_grid", ctypes.c_int)]
 
 
 class prx_plan_info(ctypes.Structure):

@@ -432,3 +432,19 @@ def test_binding_rejects_mismatched_state_tensors():
         P.prx_batch_run([0, 0], [6], [s], P.PRX_C64, [0], ws)
     P.prx_batch_destroy(b)
     P.prx_sched_destroy(s)
+
+
+def test_max_grid_caps_every_sweep_launch():
+    n = 16
+    x, z, phi = synth.random_pauli_rotations(n, 80, seed=4)
+    s = P.prx_sched_from_rotations(n, x, z, phi)
+    for kernel, opts in ((P.PRX_PLAIN, dict(max_grid=3)),
+                         (P.PRX_FUSED, dict(tile_qubits=10, chunk_rank=4, max_grid=5)),
+                         (P.PRX_FUSED, dict(max_grid=1 << 30))):
+        pl = P.prx_plan_create(s, n, P.PRX_C64, 0, 80, kernel, opts)
+        info = P.prx_plan_get_info(pl)
+        cap = min(opts["max_grid"], 1 << 22)
+        for i in range(info["passes"]):
+            assert 1 <= P.prx_plan_pass(pl, i)["grid_blocks"] <= cap
+        P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)

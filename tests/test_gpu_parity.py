@@ -283,3 +283,36 @@ def test_jw_trotter_n20_suffix_against_oracle(dtype):
         assert rel_err(out, ref) <= c64_tol(len(rx)) and abs(ov - ref[k0]) <= 1e-4
     P.prx_sched_destroy(s)
     P.prx_ham_destroy(H)
+
+
+@pytest.mark.parametrize("dtype,kernel,opts,n", [
+    # non-persistent tile kernel: 2^(16-10) = 64 tile-sets over 4 workgroups
+    (P.PRX_C64, P.PRX_FUSED, dict(tile_qubits=10, chunk_rank=4, max_virtual=6, max_grid=4), 16),
+    (P.PRX_C128, P.PRX_FUSED, dict(tile_qubits=11, max_virtual=7, max_grid=5), 16),
+    # persistent 14-qubit tile kernel: 16 tile-sets over 3 workgroups
+    (P.PRX_C64, P.PRX_FUSED, dict(tile_qubits=14, max_virtual=10, max_grid=3), 18),
+    # span passes only (a frame larger than the state) and the plain sweeps
+    (P.PRX_C128, P.PRX_FUSED, dict(tile_qubits=15, span_max=4, max_grid=3), 14),
+    (P.PRX_C64, P.PRX_PLAIN, dict(max_grid=3), 15),
+    (P.PRX_C128, P.PRX_PLAIN, dict(max_grid=2), 15),
+])
+def test_capped_grids_stride_over_the_state(dtype, kernel, opts, n):
+    """With the launch grid capped far below the work, every sweep kernel
+    strides over the rest (as at n >= 33, where the work exceeds 2^22
+    workgroups); the result equals the oracle's and, for complex128 (no
+    renormalisation, so no change in any summation order), the uncapped
+    launch's bit for bit."""
+    M = 300
+    x, z, phi = synth.random_pauli_rotations(n, M, seed=200 + n)
+    psi0 = synth.gaussian_state(n, n + 1)
+    ref = sv.c_apply_rotations(psi0, x, z, phi)
+    print(f"[capped grid n={n} dtype={dtype} kernel={kernel} opts={opts}]", flush=True)
+    t, info = _run_both(n, x, z, phi, psi0, dtype, kernel, opts)
+    got = to_host(t)
+    tol = 1e-12 if dtype == P.PRX_C128 else c64_tol(M)
+    assert rel_err(got, ref) <= tol
+    full = dict(opts)
+    full.pop("max_grid")
+    u, _ = _run_both(n, x, z, phi, psi0, dtype, kernel, full)
+    if dtype == P.PRX_C128:
+        assert np.array_equal(got, to_host(u))
