@@ -64,25 +64,33 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_trotter1_n32_c64.txt")
+def _profile_value(fname: str, kernel: str, key: str):
+    """A `key = value` line of a committed rocprofv3 counter summary under
+    profiles/, if the summary was taken on the current kernel sources and
+    for `kernel`; else None."""
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if "=" in line and not line.startswith("#"):
-            k, v = line.split("=", 1)
+        line = line.lstrip("# ").rstrip()
+        if " = " in line:
+            k, v = line.split(" = ", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_sources") != kernel_sources_digest():
         return None
     if vals.get("kernel") != kernel:
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(kernel: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the
+    committed counter summary, if taken on the current kernel sources."""
+    return _profile_value("traffic_trotter1_n32_c64.txt", kernel, "hbm_bytes_per_launch")
 
 
 def cpu_model() -> str:
@@ -527,6 +535,7 @@ def main() -> int:
     dom_name, dom_cnt, dom_avg_ms = _dominant(per_kernel)
     achieved = bytes_per_pass / (dom_avg_ms * 1e-3) / 1e9
     traffic = read_traffic(dom_name)
+    valu_busy = _profile_value("sq_counters_trotter1_n32_c64.md", dom_name, "valu_busy")
     all_pass_bw = args.steps * info["passes"] * bytes_per_pass / wall / 1e9
     del psi
     torch.cuda.empty_cache()
@@ -668,6 +677,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "valu_busy": valu_busy,
             "kernel": dom_name,
             "launches": dom_cnt,
             "avg_launch_ms": dom_avg_ms,
