@@ -82,6 +82,19 @@ __device__ __forceinline__ void gstore(uint64_t psi, uint64_t i, const Cx<T> &a)
     v.y = a.im;
     __builtin_nontemporal_store(v, ((__attribute__((address_space(1))) V2<T> *)psi) + i);
 }
+// 16 bytes per lane: G = 16 / sizeof(Cx<T>) consecutive amplitudes from
+// amplitude index i (a multiple of G).
+template <typename T>
+using V16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+template <typename T>
+__device__ __forceinline__ V16<T> gload16(uint64_t psi, uint64_t i) {
+    return __builtin_nontemporal_load(
+        (const __attribute__((address_space(1))) V16<T> *)(psi + i * sizeof(Cx<T>)));
+}
+template <typename T>
+__device__ __forceinline__ void gstore16(uint64_t psi, uint64_t i, const V16<T> &v) {
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) V16<T> *)(psi + i * sizeof(Cx<T>)));
+}
 
 // Round p: items j in [0, prefixQ[active]) over the first `active` sorted
 // samples; item j is slice j - prefixQ[k] of sorted sample k.
@@ -183,33 +196,35 @@ __global__ void __launch_bounds__(1 << (B - M))
         const int b = ta->b, g = ta->g;
         uint64_t tb = w;
         for (int i = 0; i < g; ++i) tb = insert_zero64(tb, (uint32_t)(ta->tpivots >> (6 * i)) & 63u);
+        // 16-byte groups of G slots: thread tid's group j holds slots
+        // G (tid + j NT) .. + G - 1 (see k_tile)
+        constexpr int G = 16 / (int)sizeof(Cx<T>);
+        constexpr int GPER = PER / G;
+        static_assert(sizeof(V16<T>) == 16 && sizeof(V16<T>) == G * sizeof(Cx<T>), "16-byte groups");
+        V16<T> *lds_v = reinterpret_cast<V16<T> *>(lds);
+        const uint32_t gtid = (uint32_t)G * tid;
         uint64_t c = tb;
-        const uint32_t v = tid >> b;
+        const uint32_t v = gtid >> b;
         for (int i = 0; i < g; ++i)
             if (v >> i & 1) c ^= ta->vmask[i];
-        const uint64_t base = (c << b) | (tid & ((1u << b) - 1u));
+        const uint64_t base = (c << b) | (gtid & ((1u << b) - 1u));
         {
-            Cx<T> r[PER];
+            V16<T> r[GPER];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) r[u] = gload<T>(psi, base ^ ta->uoff[u]);
+            for (int j = 0; j < GPER; ++j) r[j] = gload16<T>(psi, base ^ ta->uoff[G * j]);
 #pragma unroll
-            for (int u = 0; u < PER; ++u) lds[tid + (uint32_t)u * NT] = r[u];
+            for (int j = 0; j < GPER; ++j) lds_v[tid + (uint32_t)j * NT] = r[j];
         }
         __syncthreads();
         tile_chunks<T, B, M>(lds_raw, tmask, tb, chunks + ta->chunk_begin, ta->chunk_count,
                              reinterpret_cast<const RotRec<T> *>(rot_table));
         const T s = (T)ta->scale;
         {
-            Cx<T> q[PER];
+            V16<T> q[GPER];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) q[u] = lds[tid + (uint32_t)u * NT];
+            for (int j = 0; j < GPER; ++j) q[j] = lds_v[tid + (uint32_t)j * NT];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                Cx<T> o = q[u];
-                o.re *= s;
-                o.im *= s;
-                gstore<T>(psi, base ^ ta->uoff[u], o);
-            }
+            for (int j = 0; j < GPER; ++j) gstore16<T>(psi, base ^ ta->uoff[G * j], q[j] * s);
         }
         __syncthreads();  // the next item overwrites the LDS
     }
