@@ -87,6 +87,15 @@ def _profile_value(fname: str, kernel: str, key: str):
         return None
 
 
+def limiter(hbm_frac: float, valu_busy):
+    """The unit that the counters show closest to saturation for the dominant
+    kernel: "valu" when its vector ALU busy fraction (shader counters) is
+    above its HBM fraction of peak, else "hbm"; "hbm" without counters."""
+    if valu_busy is not None and valu_busy > hbm_frac:
+        return "valu"
+    return "hbm"
+
+
 def read_traffic(kernel: str):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the
     committed counter summary, if taken on the current kernel sources."""
@@ -678,6 +687,7 @@ def main() -> int:
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "valu_busy": valu_busy,
+            "limiter": limiter(achieved / HBM_PEAK_GBS, valu_busy),
             "kernel": dom_name,
             "launches": dom_cnt,
             "avg_launch_ms": dom_avg_ms,
