@@ -167,15 +167,16 @@ __global__ void __launch_bounds__(256) k_span(Cx<T> *__restrict__ psi, SpanArgs 
 
 // ------------------------------------------------------------------ tile
 
-// A 14-qubit complex64 tile-set fills 128 KiB of the CU's 160 KiB of LDS,
-// so one workgroup runs per CU; it runs persistently, striding over the
-// tile-sets and loading the next one into registers while it computes the
-// current one.  Smaller tile-sets run one workgroup per tile-set (two to
-// five per CU), which overlaps loads and compute across workgroups; with
-// 13-qubit tile-sets that is 7 % faster than the persistent form.
+// A 128 KiB tile-set (14 qubits at complex64, 13 at complex128) fills most
+// of the CU's 160 KiB of LDS, so one workgroup runs per CU; it runs
+// persistently, striding over the tile-sets and loading the next one into
+// registers while it computes the current one.  Smaller tile-sets run one
+// workgroup per tile-set (two to five per CU), which overlaps loads and
+// compute across workgroups; with 13-qubit complex64 tile-sets that is 7 %
+// faster than the persistent form.
 template <typename T, int B>
 struct TilePersist {
-    static constexpr bool value = sizeof(T) == 4 && B >= 14;
+    static constexpr bool value = (sizeof(Cx<T>) << B) >= (128u << 10);
 };
 
 // State access of a tile pass, 16 bytes per lane and instruction: a lane
@@ -295,9 +296,9 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
         const uint64_t tb = tile_of(w);
         const uint64_t base = base_of(tb);
         if (!PERSIST) {
-            // one set per iteration (several when the grid is capped): every
-            // thread has stored the previous set before it is overwritten
-            if (w >= gridDim.x) __syncthreads();
+            // one set per iteration (several when the grid is capped); a
+            // thread writes only the slots it read in the previous store
+            // epilogue, so no barrier is needed before the staging
             load_set(base);
             stage_set();
             __syncthreads();
@@ -322,7 +323,9 @@ __global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, 
             }
         }
         if (next) {
-            __syncthreads();  // every thread has read the finished set
+            // the staging writes exactly the slots this thread read in the
+            // store epilogue above (LDS operations of a wave stay in order),
+            // so only the chunk gathers of the next set wait at a barrier
             stage_set();
             __syncthreads();
         }
@@ -629,7 +632,11 @@ hipError_t launch_span(prx_dtype dt, int m, void *psi, const SpanArgs &a, const 
 #define PRX_TILE_SHAPES(X) X(10, 3) X(10, 4) X(11, 4) X(12, 4) X(12, 5) X(13, 4) X(13, 5) X(14, 4)
 
 bool tile_supported(prx_dtype dt, int B, int m) {
-#define PRX_TS(BB, MM) if (B == BB && m == MM) return dt == PRX_C64 || BB <= 12;
+// complex128 tile-sets up to 12 qubits, and 13 qubits (128 KiB) with rank-4
+// chunks (rank 5 would need 256 registers per lane for the set and its
+// prefetch)
+#define PRX_TS(BB, MM) \
+    if (B == BB && m == MM) return dt == PRX_C64 || BB <= 12 || (BB == 13 && MM == 4);
     PRX_TILE_SHAPES(PRX_TS)
 #undef PRX_TS
     return false;
@@ -654,7 +661,7 @@ static hipError_t tile_t(int B, int m, void *psi, const TileArgs &a, const void 
                          unsigned *blocks, unsigned cap) {
 #define PRX_TL(BB, MM)                                                                         \
     if (B == BB && m == MM) {                                                                  \
-        if constexpr (sizeof(T) == 4 || BB <= 12)                                              \
+        if constexpr (sizeof(T) == 4 || BB <= 12 || (BB == 13 && MM == 4))                    \
             return tile_launch_one<T, BB, MM>(psi, a, rots, chunks, rin, nout, s, blocks, cap); \
         return hipErrorInvalidValue;                                                      \
     }

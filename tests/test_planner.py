@@ -91,6 +91,7 @@ def test_interpreter_matches_oracle_random(n, M, dtype, opts):
     (14, dict(tile_qubits=12, chunk_rank=5)), (14, dict(commuting=1)), (14, dict(max_fuse=7)),
     (16, dict(tile_qubits=10, chunk_rank=4, max_virtual=6)),
     (18, dict(tile_qubits=12, chunk_rank=4, max_virtual=6, span_max=2)),
+    (16, dict(tile_qubits=13, chunk_rank=4, max_virtual=3, span_max=2)),
 ])
 def test_interpreter_matches_oracle_jw_trotter(n, opts):
     x, z, h = synth.jw_hamiltonian(n, 300, 7)
