@@ -360,6 +360,15 @@ __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t
 // of tid), applies the chunk's rotations, multiplies by the pending factors
 // of the coset labels and scatters back; a barrier separates chunks.
 
+// a ^ (m & c) in one gfx950 three-input bit operation (truth table 0x78
+// over the inputs a, m, c taken as bits 2, 1, 0 of the table index); the
+// compiler emits an AND and an XOR for the chunk representative otherwise.
+__device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t m, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x78" : "=v"(r) : "v"(a), "v"(m), "s"(c));
+    return r;
+}
+
 // All-ones masks of the thread index bits: a chunk's representative is then
 // one AND-XOR per bit (pinned in registers).
 template <int NB>
@@ -378,7 +387,7 @@ __device__ __forceinline__ void tile_chunks(unsigned char *lds_raw, const uint32
         const ChunkRec ch = chunks[c];
         uint32_t k0 = 0;
 #pragma unroll
-        for (int i = 0; i < B - M; ++i) k0 ^= tmask[i] & ch.cvec[i];
+        for (int i = 0; i < B - M; ++i) k0 = xor_and(k0, tmask[i], (uint32_t)ch.cvec[i]);
         const uint32_t k0b = k0 << SH;
         uint32_t Xb[1 << M];
         Xb[0] = 0;
