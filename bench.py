@@ -146,6 +146,40 @@ def _trotter1_n28_rotations():
     return w["n"], rx, rz, rp, synth.basis_index(w["n"])
 
 
+def full_small_runs():
+    """The oracle on two whole small workloads, all cores: the 14-qubit
+    random-rotation case (1000 rotations from a Gaussian state) and the
+    n = 20 check of the n = 32 Trotter workload (same H recipe with its own
+    seed, 4 steps of 5000 rotations)."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import synth
+    from oracle import schedules as osch
+    from oracle import statevector as sv
+    out = {}
+    w = synth.WORKLOADS["random_n14"]
+    x, z, phi = synth.random_pauli_rotations(w["n"], w["M"], w["rot_seed"])
+    psi = synth.gaussian_state(w["n"], w["state_seed"])
+    t0 = time.perf_counter()
+    sv.c_apply_rotations(psi, x, z, phi, out=psi)
+    dt = time.perf_counter() - t0
+    out["random_n14"] = {"rotations": int(w["M"]), "seconds": dt,
+                         "value": w["M"] * float(1 << w["n"]) / dt, "cores": sv.c_threads()}
+    w = synth.WORKLOADS["trotter1_n32"]
+    n = w["check_n"]
+    x, z, h = synth.jw_hamiltonian(n, w["L"], w["check_seed"])
+    rx, rz, rp = osch.trotter(x, z, h, 1, w["t"], w["steps"], suffix=True)
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[synth.basis_index(n)] = 1.0
+    t0 = time.perf_counter()
+    sv.c_apply_rotations(psi, rx, rz, rp, out=psi)
+    dt = time.perf_counter() - t0
+    out["trotter1_n20_check"] = {"rotations": len(rx), "seconds": dt,
+                                 "value": len(rx) * float(1 << n) / dt,
+                                 "cores": sv.c_threads()}
+    return out
+
+
 def one_core_worker(budget_s: float) -> int:
     """Child process (OMP_NUM_THREADS=1): the oracle on one core, first
     rotations of the n = 28 Trotter workload; prints one JSON line."""
@@ -158,7 +192,8 @@ def one_core_worker(budget_s: float) -> int:
 def cpu_baseline(x, z, phi, n: int, k0: int, budget_s: float, max_rot: int):
     """The oracle as it stands: all cores on the first rotations of the
     benchmark schedule; one core (child process) and all cores on the n = 28
-    Trotter workload's first rotations (at most 100)."""
+    Trotter workload's first rotations (at most 100); all cores on two whole
+    small workloads (full_small_runs)."""
     import subprocess
     done, dt, thr = _oracle_rate(x, z, phi, n, k0, budget_s, max_rot)
     out = {
@@ -176,6 +211,7 @@ def cpu_baseline(x, z, phi, n: int, k0: int, budget_s: float, max_rot: int):
     d2, t2, thr2 = _oracle_rate(rx, rz, rp, n28, b28, budget_s, 100)
     out["n28_rate"] = {"value": d2 * float(1 << n28) / t2, "cores": thr2, "rotations": d2,
                        "seconds": t2, "sample": "rotations 1.. of the n=28 Trotter workload (rotation 0 untimed)"}
+    out["full_runs"] = full_small_runs()
     env = dict(os.environ, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, os.path.abspath(__file__), "--one-core-worker",
                         "--cpu-budget", str(budget_s / 2)], env=env, capture_output=True,

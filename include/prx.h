@@ -386,6 +386,12 @@ prx_status prx_batch_upload(prx_batch *b, void *const *psi, void *ws, size_t ws_
  * replayed and captured in one graph (prx_batch_graph). */
 prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
                              double *overlaps_dev, void *stream);
+/* Caps the grid of every round launch at max_grid workgroups (0 restores
+ * the defaults: 2^20 for the tile rounds, 8 per CU for the span rounds);
+ * each launch then strides over the rest of its items.  The results do not
+ * depend on the cap.  Takes effect at the next prx_batch_execute or
+ * prx_batch_graph.  INVALID for a null batch. */
+prx_status prx_batch_set_max_grid(prx_batch *b, unsigned max_grid);
 /* Waits for the stream and reports any pending HIP error. */
 prx_status prx_batch_check(const prx_batch *b, const void *ws, void *stream);
 void prx_batch_destroy(prx_batch *b);

@@ -263,6 +263,7 @@ struct prx_batch {
     std::vector<uint32_t> tround_active;
     uint64_t total_items = 0, total_tile_items = 0;
     uint32_t rounds = 0;
+    unsigned max_grid = 0;  // 0: the default grid caps
     // workspace layout
     size_t off_samples = 0, off_passes = 0, off_rots = 0, off_prefix = 0, off_order = 0,
            off_tsamples = 0, off_tpasses = 0, off_tchunks = 0, off_tprefix = 0, off_torder = 0,
@@ -516,13 +517,18 @@ prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
     int dev = 0, cus = 256;
     PRX_HIP(hipGetDevice(&dev));
     PRX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const uint64_t cap = (uint64_t)std::max(1, cus) * 8u;
+    uint64_t cap = (uint64_t)std::max(1, cus) * 8u;
+    uint64_t tcap = kTileGridCap;
+    if (b->max_grid) {
+        cap = std::min<uint64_t>(cap, b->max_grid);
+        tcap = std::min<uint64_t>(tcap, b->max_grid);
+    }
     const unsigned tile_threads = 1u << (batch_tile_qubits(b->dtype) - kBatchTileM);
     for (uint32_t p = 0; p < b->rounds; ++p) {
         const uint32_t tactive = b->tround_active[p];
         const uint64_t titems = b->tprefix[tactive];
         if (titems) {
-            const unsigned grid = (unsigned)std::min<uint64_t>(titems, kTileGridCap);
+            const unsigned grid = (unsigned)std::min<uint64_t>(titems, tcap);
             if (b->dtype == PRX_C64)
                 hipLaunchKernelGGL((k_batch_tile_round<float, 12, kBatchTileM>), dim3(grid),
                                    dim3(tile_threads), 0, st, ta.samples, ta.passes, ta.chunks,
@@ -554,6 +560,12 @@ prx_status prx_batch_execute(const prx_batch *b, void *ws, size_t ws_bytes,
         hipLaunchKernelGGL(k_batch_overlaps<double>, dim3(rb), dim3(256), 0, st, a.samples,
                            (uint32_t)b->S, overlaps_dev);
     PRX_HIP(hipGetLastError());
+    return PRX_OK;
+}
+
+prx_status prx_batch_set_max_grid(prx_batch *b, unsigned max_grid) {
+    if (!b) return fail(PRX_ERR_INVALID, "null batch");
+    b->max_grid = max_grid;
     return PRX_OK;
 }
 

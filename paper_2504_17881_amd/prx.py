@@ -153,6 +153,7 @@ _sig("prx_batch_upload", _st, _vp, ctypes.POINTER(_vp), _vp, _sz, _vp)
 _sig("prx_batch_execute", _st, _vp, _vp, _sz, _vp, _vp)
 _sig("prx_batch_check", _st, _vp, _vp, _vp)
 _sig("prx_batch_destroy", None, _vp)
+_sig("prx_batch_set_max_grid", _st, _vp, ctypes.c_uint)
 _sig("prx_batch_run", _st, _sz, ctypes.POINTER(_vp), ctypes.POINTER(_i), ctypes.POINTER(_vp),
      _i, _u64p, _dp, _vp, _sz, _vp)
 _sig("prx_batch_graph", _st, _vp, _vp, _sz, _vp, _vp, ctypes.POINTER(_vp))
@@ -530,6 +531,10 @@ def prx_batch_execute(batch: int, ws, overlaps_dev, stream=None, ws_bytes=None) 
     _check(_lib.prx_batch_execute(batch, _device_buf(ws), _nbytes(ws, ws_bytes),
                                   _device_buf(overlaps_dev, "overlaps"),
                                   _stream(stream)))
+
+
+def prx_batch_set_max_grid(batch: int, max_grid: int) -> None:
+    _check(_lib.prx_batch_set_max_grid(batch, int(max_grid)))
 
 
 def prx_batch_check(batch: int, ws, stream=None) -> None:

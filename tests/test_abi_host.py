@@ -200,7 +200,12 @@ def test_batch_create_host_checks():
     basis = [synth.basis_index(n) for n in ns]
     b = P.prx_batch_create(ns, scheds, P.PRX_C64, basis)
     assert P.prx_batch_workspace_bytes(b) > 0
+    P.prx_batch_set_max_grid(b, 3)
+    P.prx_batch_set_max_grid(b, 0)
     P.prx_batch_destroy(b)
+    with pytest.raises(P.PrxError) as e:
+        P.prx_batch_set_max_grid(None, 3)
+    assert e.value.status == P.PRX_ERR_INVALID
     for bad_n, bad_b in [([6, 8, 5], basis), (ns, [0, 1 << 8, 0]), ([6, 9, 7], basis)]:
         with pytest.raises(P.PrxError) as e:
             P.prx_batch_create(bad_n, scheds, P.PRX_C64, bad_b)

@@ -99,6 +99,46 @@ def test_tile_rounds_with_many_virtual_qubits(dtype):
     _free(hams, scheds)
 
 
+@pytest.mark.parametrize("dtype", [P.PRX_C128, P.PRX_C64])
+def test_capped_round_grids_stride_over_the_items(dtype):
+    """With every round launch capped at 3 workgroups, both round kernels
+    stride over their items (the tile rounds hold several tile-sets per
+    workgroup in turn); the states equal the oracle's and, for complex128,
+    the uncapped launch's bit for bit."""
+    ns = [14, 9, 13, 7, 12, 11]
+    N = 200
+    hams, scheds = _inputs(ns, 80, N, 0.9, seed0=300)
+    basis = [synth.basis_index(n) for n in ns]
+    runs = []
+    for cap in (3, 0):
+        psis = [basis_state(n, b0, dtype) for n, b0 in zip(ns, basis)]
+        b = P.prx_batch_create(ns, scheds, dtype, basis)
+        P.prx_batch_set_max_grid(b, cap)
+        ws = workspace(P.prx_batch_workspace_bytes(b))
+        ovd = torch.zeros(2 * len(ns), dtype=torch.float64, device=dev())
+        P.prx_batch_upload(b, psis, ws)
+        print(f"[capped rounds dtype={dtype} cap={cap}] launching", flush=True)
+        P.prx_batch_execute(b, ws, ovd)
+        P.prx_batch_check(b, ws)
+        print(f"[capped rounds dtype={dtype} cap={cap}] done", flush=True)
+        runs.append(([to_host(p) for p in psis], ovd.cpu().numpy()))
+        P.prx_batch_destroy(b)
+    tol = 1e-12 if dtype == P.PRX_C128 else 8 * EPS32 * math.sqrt(N) + 1e-6
+    (capped, ovc), (full, ovf) = runs
+    for i, n in enumerate(ns):
+        x, z, h, _ = hams[n]
+        rx, rz, rp = S.qdrift(x, z, h, 0.9, N, 300 + i)
+        psi0 = np.zeros(1 << n, dtype=np.complex128)
+        psi0[basis[i]] = 1
+        ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+        assert rel_err(capped[i], ref) <= tol, (i, n)
+        if dtype == P.PRX_C128:
+            assert np.array_equal(capped[i], full[i]), (i, n)
+    if dtype == P.PRX_C128:
+        assert np.array_equal(ovc, ovf)
+    _free(hams, scheds)
+
+
 def _empty_sched(n):
     e = np.array([], dtype=np.uint64)
     return P.prx_sched_from_rotations(n, e, e, np.array([], dtype=np.float64))
