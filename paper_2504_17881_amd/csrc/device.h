@@ -294,9 +294,64 @@ __device__ __forceinline__ void rot_var(Cx<T> (&amp)[1 << M], T ga, T gb, uint32
 // k0: coset representative in the frame of rec.z (32-bit in a tile frame);
 // tbase: the tile index whose parity with rec.zhigh adds to the sign (0 for
 // span passes).
+// The same variants as threaded code (rot_loop_f32m4.inc): runs the records
+// at plo:phi until cnt reaches zero or a diagonal record comes up (left
+// unconsumed); k0 is the lane's coset representative, tb the base tile
+// index.  The pointer and count are uniform; so are their new values.
+#include "rot_loop_f32m4.inc"
+__device__ __forceinline__ void rot_loop(Cx<float> (&amp)[16], uint32_t k0, uint64_t tb,
+                                         uint32_t &plo, uint32_t &phi, uint32_t &cnt) {
+    uint32_t ga, gb;
+    asm volatile(PRX_ROT_LOOP_F32M4
+        : "+v"(amp[0].re), "+v"(amp[0].im), "+v"(amp[1].re), "+v"(amp[1].im),
+          "+v"(amp[2].re), "+v"(amp[2].im), "+v"(amp[3].re), "+v"(amp[3].im),
+          "+v"(amp[4].re), "+v"(amp[4].im), "+v"(amp[5].re), "+v"(amp[5].im),
+          "+v"(amp[6].re), "+v"(amp[6].im), "+v"(amp[7].re), "+v"(amp[7].im),
+          "+v"(amp[8].re), "+v"(amp[8].im), "+v"(amp[9].re), "+v"(amp[9].im),
+          "+v"(amp[10].re), "+v"(amp[10].im), "+v"(amp[11].re), "+v"(amp[11].im),
+          "+v"(amp[12].re), "+v"(amp[12].im), "+v"(amp[13].re), "+v"(amp[13].im),
+          "+v"(amp[14].re), "+v"(amp[14].im), "+v"(amp[15].re), "+v"(amp[15].im),
+          [plo] "+s"(plo), [phi] "+s"(phi), [cnt] "+s"(cnt), [ga] "=&v"(ga), [gb] "=&v"(gb)
+        : [k0] "v"(k0), [tb] "s"(tb)
+        : "s76", "s77", "s78", "s79", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87",
+          "s88", "s89", "s90", "s91", "scc", "memory");
+    plo = __builtin_amdgcn_readfirstlane(plo);
+    phi = __builtin_amdgcn_readfirstlane(phi);
+    cnt = __builtin_amdgcn_readfirstlane(cnt);
+}
+
 template <typename T, int M, typename K0>
 __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t tbase,
                                            const RotRec<T> *__restrict__ rots, uint32_t count) {
+    if constexpr (sizeof(T) == 4 && M == 4 && sizeof(K0) == 4) {
+        // tile chunks at complex64: the threaded loop, stopping for the
+        // diagonal records, which take the compiled path below
+        const uint64_t p0 = (uint64_t)rots;
+        uint32_t plo = __builtin_amdgcn_readfirstlane((uint32_t)p0);
+        uint32_t phi = __builtin_amdgcn_readfirstlane((uint32_t)(p0 >> 32));
+        uint32_t cnt = __builtin_amdgcn_readfirstlane(count);
+        while (true) {
+            rot_loop(amp, k0, tbase, plo, phi, cnt);
+            if (cnt == 0u) break;
+            const RotRec<T> *rp =
+                reinterpret_cast<const RotRec<T> *>(((uint64_t)phi << 32) | plo);
+            const RotRec<T> rec = *rp;
+            const uint32_t zeta = (rec.info >> 8) & 0xffu;
+            const uint32_t tpar =
+                __builtin_amdgcn_readfirstlane((uint32_t)__builtin_popcountll(tbase & rec.zhigh));
+            uint32_t c, ua;
+            asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(c) : "v"(k0 & (uint32_t)rec.z), "s"(tpar));
+            asm("v_lshl_add_u32 %0, %1, 31, %2"
+                : "=v"(ua)
+                : "v"(c), "s"(__builtin_amdgcn_readfirstlane(__float_as_uint(rec.tau_a))));
+            rot_diag<T, M>(amp, __uint_as_float(ua), zeta);
+            const uint64_t pn = (((uint64_t)phi << 32) | plo) + sizeof(RotRec<T>);
+            plo = (uint32_t)pn;
+            phi = (uint32_t)(pn >> 32);
+            cnt -= 1u;
+        }
+        return;
+    }
     for (uint32_t r = 0; r < count; ++r) {
         const RotRec<T> rec = rots[r];
         const uint32_t slot = rec.info & 15u;

@@ -13,21 +13,37 @@ its table instead of walking a branch tree.
 
 Operands of the generated block: %0..%31 the amplitudes (re, im of amp[0],
 amp[1], ...), %32 a scratch SGPR, %33 ga, %34 gb, %35 var; it clobbers
-s[90:91] and SCC.  Run from this directory: python3 gen_rot_jump.py
+s[90:91] and SCC.
+
+It also writes rot_loop_f32m4.inc: a whole run of rotations of a tile
+chunk as one block of threaded code.  The header loads the next 32-byte
+rotation record with one scalar load, computes the lane's sign and the two
+coefficients and jumps to its variant; each variant ends with the loop test
+and a branch straight back to the header, so a rotation takes one computed
+jump and one taken branch instead of a call into the table, a branch out of
+it and the compiled loop's own control flow.  A diagonal record (var = 64)
+leaves the block without being consumed (the caller applies it), as does
+the end of the run.  Variants are 32 v_fma_f32, s_cmp_lg_u32, s_cbranch_scc1
+and s_branch: 268 bytes.  Operands: %0..%31 the amplitudes, %[plo], %[phi]
+the record pointer and %[cnt] the records left (read and written), %[ga],
+%[gb] scratch, %[k0] the lane's coset representative, %[tb] the base tile
+index; it clobbers s[76:91] and SCC.
+
+Run from this directory: python3 gen_rot_jump.py
 """
 import os
 
 M = 4
 VARIANT_BYTES = 32 * 8 + 4
+LOOP_VARIANT_BYTES = 32 * 8 + 3 * 4
 
 
 def drop_bit(v, i):
     return ((v >> (i + 1)) << i) | (v & ((1 << i) - 1))
 
 
-def pair(v, w, imag, neg):
+def pair(v, w, imag, neg, ga="%33", gb="%34"):
     ar, ai, br, bi = f"%{2 * v}", f"%{2 * v + 1}", f"%{2 * w}", f"%{2 * w + 1}"
-    ga, gb = "%33", "%34"
     n = "-" if neg else ""
     p = "" if neg else "-"
     if not imag:
@@ -42,17 +58,20 @@ def pair(v, w, imag, neg):
             f"v_fma_f32 {bi}, {n}{gb}, {ar}, {bi}"]
 
 
-def variant(var):
+def fmas(var, ga="%33", gb="%34"):
     slot, imag, zp = var >> M, (var >> (M - 1)) & 1, var & ((1 << (M - 1)) - 1)
     out = []
     for v in range(1 << M):
         if v >> slot & 1:
             continue
         neg = bin(drop_bit(v, slot) & zp).count("1") & 1
-        out += pair(v, v | (1 << slot), imag, neg)
-    out.append("s_branch 3f")
-    assert len(out) == 33
+        out += pair(v, v | (1 << slot), imag, neg, ga, gb)
+    assert len(out) == 32
     return out
+
+
+def variant(var):
+    return fmas(var) + ["s_branch 3f"]
 
 
 def block():
@@ -72,6 +91,44 @@ def block():
     return lines
 
 
+def loop_block():
+    lines = ["s_mov_b32 s76, %[plo]",          # record pointer and count in
+             "s_mov_b32 s77, %[phi]",          # fixed registers
+             "s_mov_b32 s78, %[cnt]",
+             "s_cmp_eq_u32 s78, 0",
+             "s_cbranch_scc1 9f",
+             "8:",                             # header: next record
+             "s_load_dwordx8 s[80:87], s[76:77], 0x0",
+             "s_waitcnt lgkmcnt(0)",
+             "s_bfe_u32 s88, s84, 0x80010",    # var = info bits 16..23
+             "s_cmp_eq_u32 s88, 64",
+             "s_cbranch_scc1 9f",              # diagonal: leave it to the caller
+             "s_and_b64 s[82:83], s[82:83], %[tb]",
+             "s_bcnt1_i32_b64 s89, s[82:83]",  # parity(tile & zhigh) in bit 0
+             "v_and_b32 %[ga], s80, %[k0]",
+             "v_bcnt_u32_b32 %[ga], %[ga], s89",
+             "v_lshl_add_u32 %[gb], %[ga], 31, s87",
+             "v_lshl_add_u32 %[ga], %[ga], 31, s86",
+             "s_add_u32 s76, s76, 32",
+             "s_addc_u32 s77, s77, 0",
+             "s_sub_u32 s78, s78, 1",
+             "s_min_u32 s88, s88, 63",
+             f"s_mul_i32 s88, s88, {LOOP_VARIANT_BYTES}",
+             "s_getpc_b64 s[90:91]",
+             "1:",
+             "s_add_u32 s90, s90, s88",
+             "s_addc_u32 s91, s91, 0",
+             "s_add_u32 s90, s90, (2f - 1b)",
+             "s_addc_u32 s91, s91, 0",
+             "s_setpc_b64 s[90:91]",
+             "2:"]
+    for var in range(M << M):
+        lines += fmas(var, "%[ga]", "%[gb]") + ["s_cmp_lg_u32 s78, 0", "s_cbranch_scc1 8b",
+                                                "s_branch 9f"]
+    lines += ["9:", "s_mov_b32 %[plo], s76", "s_mov_b32 %[phi], s77", "s_mov_b32 %[cnt], s78"]
+    return lines
+
+
 def main():
     here = os.path.dirname(os.path.abspath(__file__))
     text = ("// Generated by gen_rot_jump.py; do not edit.\n"
@@ -82,6 +139,15 @@ def main():
             "#define PRX_ROT_JUMP_F32M4 \\\n" + " \\\n".join(
                 f'    "{line}\\n"' for line in block()) + "\n")
     with open(os.path.join(here, "rot_jump_f32m4.inc"), "w") as f:
+        f.write(text)
+    text = ("// Generated by gen_rot_jump.py; do not edit.\n"
+            "// Threaded rotation loop over the 64 complex64 rank-4 static-sign\n"
+            "// variants (operands and layout: see gen_rot_jump.py).\n"
+            "#pragma once\n"
+            f"#define PRX_ROT_LOOP_VARIANT_BYTES {LOOP_VARIANT_BYTES}\n"
+            "#define PRX_ROT_LOOP_F32M4 \\\n" + " \\\n".join(
+                f'    "{line}\\n"' for line in loop_block()) + "\n")
+    with open(os.path.join(here, "rot_loop_f32m4.inc"), "w") as f:
         f.write(text)
 
 

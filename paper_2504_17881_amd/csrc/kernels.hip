@@ -211,8 +211,19 @@ __device__ __forceinline__ void group_store(Cx<T> *p, const typename Group<T>::V
         *reinterpret_cast<V *>(p) = v;
 }
 
+// Waves per SIMD that the LDS allows a tile shape (tile-sets per CU x waves
+// per set / 4 SIMDs), the occupancy the register allocation is asked to
+// keep: five 12-qubit complex64 workgroups per CU need at most 96 registers.
 template <typename T, int B, int M>
-__global__ void __launch_bounds__(1 << (B - M)) k_tile(Cx<T> *__restrict__ psi, TileArgs a,
+struct TileWaves {
+    static constexpr unsigned sets = (160u << 10) / (sizeof(Cx<T>) << B);
+    static constexpr unsigned w = sets * ((1u << (B - M)) / 64u) / 4u;
+    static constexpr unsigned value = w < 1 ? 1 : (w > 8 ? 8 : w);
+};
+
+template <typename T, int B, int M>
+__global__ void __launch_bounds__(1 << (B - M))
+    __attribute__((amdgpu_waves_per_eu(TileWaves<T, B, M>::value))) k_tile(Cx<T> *__restrict__ psi, TileArgs a,
                                                       const RotRec<T> *__restrict__ rots,
                                                       const ChunkRec *__restrict__ chunks,
                                                       const double *__restrict__ renorm_in,

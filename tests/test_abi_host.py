@@ -285,6 +285,22 @@ def test_rotation_jump_table_is_generated_from_its_script(tmp_path):
         dst = [x.split()[1].rstrip(",") for x in v[:32]]
         assert sorted(dst) == sorted(f"%{i}" for i in range(32))
     assert lines[0] == "s_min_u32 %32, %35, 63" and gen.VARIANT_BYTES == 260
+    # the threaded loop: same FMAs per variant, then the loop test and exits
+    with open(tmp_path / "rot_loop_f32m4.inc") as f, open(os.path.join(csrc, "rot_loop_f32m4.inc")) as g:
+        assert f.read() == g.read()
+    loop = gen.loop_block()
+    start, end = loop.index("2:"), loop.index("9:")
+    body = loop[start + 1:end]
+    assert len(body) == 64 * 35 and gen.LOOP_VARIANT_BYTES == 268
+    for var in range(64):
+        v = body[35 * var:35 * (var + 1)]
+        assert [x.replace("%[ga]", "%33").replace("%[gb]", "%34") for x in v[:32]] == \
+            gen.variant(var)[:32]
+        assert v[32:] == ["s_cmp_lg_u32 s78, 0", "s_cbranch_scc1 8b", "s_branch 9f"]
+    # the diagonal variant index leaves before the jump; the count is tested
+    # on entry and after every rotation
+    assert loop.index("s_cmp_eq_u32 s88, 64") < loop.index("s_setpc_b64 s[90:91]")
+    assert loop[3:5] == ["s_cmp_eq_u32 s78, 0", "s_cbranch_scc1 9f"]
 
 
 def _code_object(tmp_path, obj_name):
@@ -315,44 +331,75 @@ def _code_object(tmp_path, obj_name):
     return ins
 
 
+def _branch_target(ins, j):
+    """Target address of the SOPP branch at instruction j (simm16 in dwords,
+    relative to the next instruction)."""
+    off = int(ins[j][2].split()[-1], 0)
+    if off >= 1 << 15:
+        off -= 1 << 16
+    return ins[j][0] + 4 + 4 * off
+
+
 @pytest.mark.parametrize("obj_name", ["kernels.hip.o", "batch.hip.o"])
 def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
     """Every instance of the computed jump in the built gfx950 code: the
-    table starts right after s_setpc_b64, variant v occupies bytes
-    [260 v, 260 (v + 1)) of it as 32 eight-byte v_fma_f32 and one s_branch
-    to the table's end, and the jump adds (table - return address) and
-    260 * min(var, 63) to the return address.  A different encoding size
-    would send the jump into the middle of an instruction."""
+    table starts right after s_setpc_b64 and the jump adds (table - return
+    address) and stride * min(var, 63) to the return address.  In the
+    jump table (stride 260) variant v is 32 eight-byte v_fma_f32 and one
+    s_branch to the table's end; in the threaded loop (stride 268) it is 32
+    v_fma_f32, the count test, a branch back to the loop header (the scalar
+    load of the next record) and a branch to the exit, and every exit of the
+    loop lands on the same address.  A different encoding size would send
+    the jump into the middle of an instruction."""
     ins = _code_object(tmp_path, obj_name)
     addr = [a for a, _, _ in ins]
     at = {a: i for i, a in enumerate(addr)}
     tables = [i for i, (_, op, txt) in enumerate(ins) if op == "s_setpc_b64" and "s[90:91]" in txt]
-    assert tables, "no jump table in the code object"
+    kinds = {260: 0, 268: 0}
     for i in tables:
-        # preamble: s_min_u32, s_mul_i32 260, s_getpc_b64, s_add/addc (var),
+        # preamble: s_min_u32, s_mul_i32 stride, s_getpc_b64, s_add/addc (var),
         # s_add/addc (label offset), s_setpc_b64
         pre = [op for _, op, _ in ins[i - 7:i + 1]]
         assert pre == ["s_min_u32", "s_mul_i32", "s_getpc_b64", "s_add_u32", "s_addc_u32",
                        "s_add_u32", "s_addc_u32", "s_setpc_b64"], pre
-        assert ins[i - 7][2].endswith(", 63") and ins[i - 6][2].endswith(", 0x104")
+        assert ins[i - 7][2].endswith(", 63")
+        stride = int(ins[i - 6][2].rsplit(",", 1)[1].strip(), 0)
+        assert stride in kinds, stride
+        kinds[stride] += 1
         ret = addr[i - 4]                       # s_getpc_b64 yields the next address
         start = addr[i + 1]
         off = int(ins[i - 2][2].rsplit(",", 1)[1].strip(), 0)
         assert ret + off == start, (hex(ret), off, hex(start))
-        end = start + 64 * 260
+        end = start + 64 * stride
+        assert end in at
+        if stride == 260:
+            for var in range(64):
+                base = start + 260 * var
+                for k in range(32):
+                    j = at[base + 8 * k]
+                    assert ins[j][1] == "v_fma_f32", (var, k, ins[j])
+                j = at[base + 256]
+                assert ins[j][1] == "s_branch" and _branch_target(ins, j) == end, (var, ins[j])
+                assert addr[j + 1] == base + 260
+            continue
+        # threaded loop: the header is the record load before the jump
+        hdr = max(j for j in range(i) if ins[j][1] == "s_load_dwordx8" and "s[80:87]" in ins[j][2])
+        assert i - hdr < 40
+        exits = [j for j in range(hdr - 2, i) if ins[j][1] == "s_cbranch_scc1"]
+        assert len(exits) == 2 and all(_branch_target(ins, j) == end for j in exits)
         for var in range(64):
-            base = start + 260 * var
+            base = start + 268 * var
             for k in range(32):
                 j = at[base + 8 * k]
                 assert ins[j][1] == "v_fma_f32", (var, k, ins[j])
             j = at[base + 256]
-            assert ins[j][1] == "s_branch", (var, ins[j])
-            assert addr[j + 1] == base + 260
-        # every branch of the table lands on the table's end
-        for var in range(64):
-            j = at[start + 260 * var + 256]
-            assert re.search(r"s_branch\s+(\S+)", ins[j][2])
-        assert end in at
+            assert ins[j][1] == "s_cmp_lg_u32" and ins[j][2].endswith("s78, 0"), ins[j]
+            assert ins[j + 1][1] == "s_cbranch_scc1" and _branch_target(ins, j + 1) == addr[hdr]
+            assert ins[j + 2][1] == "s_branch" and _branch_target(ins, j + 2) == end
+            assert addr[j + 3] == base + 268
+    assert kinds[268] >= 1, "no threaded rotation loop in the code object"
+    if obj_name == "kernels.hip.o":
+        assert kinds[260] >= 1, "no jump table in the code object"
 
 
 def test_launch_grids_stay_inside_the_work_item_range():
