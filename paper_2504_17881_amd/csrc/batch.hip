@@ -416,7 +416,7 @@ prx_status prx_batch_create(size_t S, const int *n, const prx_sched *const *sche
         size_t o = 0;
         b->off_samples = o;  o = al256(o + S * sizeof(BSample));
         b->off_passes = o;   o = al256(o + b->passes.size() * sizeof(BPass));
-        b->off_rots = o;     o = al256(o + b->rots.size());
+        b->off_rots = o;     o = al256(o + b->rots.size() + kRecordReadAhead);
         b->off_prefix = o;   o = al256(o + b->prefixQ.size() * sizeof(uint64_t));
         b->off_order = o;    o = al256(o + S * sizeof(uint32_t));
         b->off_tsamples = o; o = al256(o + St * sizeof(BTSample));

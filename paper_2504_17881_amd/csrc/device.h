@@ -297,7 +297,9 @@ __device__ __forceinline__ void rot_var(Cx<T> (&amp)[1 << M], T ga, T gb, uint32
 // The same variants as threaded code (rot_loop_f32m4.inc): runs the records
 // at plo:phi until cnt reaches zero or a diagonal record comes up (left
 // unconsumed); k0 is the lane's coset representative, tb the base tile
-// index.  The pointer and count are uniform; so are their new values.
+// index.  The pointer and count are uniform; so are their new values.  It
+// loads the record after the current one early, so every rotation table is
+// followed by kRecordReadAhead readable bytes (plan and batch workspaces).
 #include "rot_loop_f32m4.inc"
 __device__ __forceinline__ void rot_loop(Cx<float> (&amp)[16], uint32_t k0, uint64_t tb,
                                          uint32_t &plo, uint32_t &phi, uint32_t &cnt) {

@@ -16,18 +16,20 @@ amp[1], ...), %32 a scratch SGPR, %33 ga, %34 gb, %35 var; it clobbers
 s[90:91] and SCC.
 
 It also writes rot_loop_f32m4.inc: a whole run of rotations of a tile
-chunk as one block of threaded code.  The header loads the next 32-byte
+chunk as one block of threaded code.  A header loads the first 32-byte
 rotation record with one scalar load, computes the lane's sign and the two
-coefficients and jumps to its variant; each variant ends with the loop test
-and a branch straight back to the header, so a rotation takes one computed
-jump and one taken branch instead of a call into the table, a branch out of
-it and the compiled loop's own control flow.  A diagonal record (var = 64)
-leaves the block without being consumed (the caller applies it), as does
-the end of the run.  Variants are 32 v_fma_f32, s_cmp_lg_u32, s_cbranch_scc1
-and s_branch: 268 bytes.  Operands: %0..%31 the amplitudes, %[plo], %[phi]
-the record pointer and %[cnt] the records left (read and written), %[ga],
-%[gb] scratch, %[k0] the lane's coset representative, %[tb] the base tile
-index; it clobbers s[76:91] and SCC.
+coefficients and jumps to its variant.  Each variant issues the load of the
+next record, applies its 32 FMAs, and then does the same dispatch for the
+next record itself, jumping straight to that record's variant: a rotation
+takes one computed jump and no other taken branch, and the record's load
+overlaps the FMAs (the table must be followed by 32 readable bytes).  The
+block is left, without consuming it, at a diagonal record (var = 64; the
+caller applies it) and at the end of the run.  Variants are 380 bytes:
+the load (8), 32 v_fma_f32, the count test and exit (8), the wait (4) and
+the dispatch (112).  Operands: %0..%31 the amplitudes, %[plo], %[phi] the
+record pointer and %[cnt] the records left (read and written), %[ga], %[gb]
+scratch, %[k0] the lane's coset representative, %[tb] the base tile index;
+it clobbers s[76:91] and SCC.
 
 Run from this directory: python3 gen_rot_jump.py
 """
@@ -35,7 +37,7 @@ import os
 
 M = 4
 VARIANT_BYTES = 32 * 8 + 4
-LOOP_VARIANT_BYTES = 32 * 8 + 3 * 4
+LOOP_VARIANT_BYTES = 32 * 8 + 124
 
 
 def drop_bit(v, i):
@@ -91,40 +93,47 @@ def block():
     return lines
 
 
+# the header that computes the lane's coefficients for the record at s[80:87]
+# and jumps to its variant; `off` is the assembler expression for the table
+# start minus the address after s_getpc_b64, `hi` the high-word carry term
+def _dispatch(off, hi):
+    return ["s_bfe_u32 s88, s84, 0x80010",    # var = info bits 16..23
+            "s_cmp_eq_u32 s88, 64",
+            "s_cbranch_scc1 9f",              # diagonal: leave it to the caller
+            "s_and_b64 s[82:83], s[82:83], %[tb]",
+            "s_bcnt1_i32_b64 s89, s[82:83]",  # parity(tile & zhigh) in bit 0
+            "v_and_b32 %[ga], s80, %[k0]",
+            "v_bcnt_u32_b32 %[ga], %[ga], s89",
+            "v_lshl_add_u32 %[gb], %[ga], 31, s87",
+            "v_lshl_add_u32 %[ga], %[ga], 31, s86",
+            "s_add_u32 s76, s76, 32",
+            "s_addc_u32 s77, s77, 0",
+            "s_sub_u32 s78, s78, 1",
+            "s_min_u32 s88, s88, 63",
+            f"s_mul_i32 s88, s88, {LOOP_VARIANT_BYTES}",
+            "s_getpc_b64 s[90:91]",
+            "1:",
+            "s_add_u32 s90, s90, s88",
+            "s_addc_u32 s91, s91, 0",
+            f"s_add_u32 s90, s90, {off}",
+            f"s_addc_u32 s91, s91, {hi}",
+            "s_setpc_b64 s[90:91]"]
+
+
 def loop_block():
     lines = ["s_mov_b32 s76, %[plo]",          # record pointer and count in
              "s_mov_b32 s77, %[phi]",          # fixed registers
              "s_mov_b32 s78, %[cnt]",
              "s_cmp_eq_u32 s78, 0",
              "s_cbranch_scc1 9f",
-             "8:",                             # header: next record
              "s_load_dwordx8 s[80:87], s[76:77], 0x0",
-             "s_waitcnt lgkmcnt(0)",
-             "s_bfe_u32 s88, s84, 0x80010",    # var = info bits 16..23
-             "s_cmp_eq_u32 s88, 64",
-             "s_cbranch_scc1 9f",              # diagonal: leave it to the caller
-             "s_and_b64 s[82:83], s[82:83], %[tb]",
-             "s_bcnt1_i32_b64 s89, s[82:83]",  # parity(tile & zhigh) in bit 0
-             "v_and_b32 %[ga], s80, %[k0]",
-             "v_bcnt_u32_b32 %[ga], %[ga], s89",
-             "v_lshl_add_u32 %[gb], %[ga], 31, s87",
-             "v_lshl_add_u32 %[ga], %[ga], 31, s86",
-             "s_add_u32 s76, s76, 32",
-             "s_addc_u32 s77, s77, 0",
-             "s_sub_u32 s78, s78, 1",
-             "s_min_u32 s88, s88, 63",
-             f"s_mul_i32 s88, s88, {LOOP_VARIANT_BYTES}",
-             "s_getpc_b64 s[90:91]",
-             "1:",
-             "s_add_u32 s90, s90, s88",
-             "s_addc_u32 s91, s91, 0",
-             "s_add_u32 s90, s90, (2f - 1b)",
-             "s_addc_u32 s91, s91, 0",
-             "s_setpc_b64 s[90:91]",
-             "2:"]
+             "s_waitcnt lgkmcnt(0)"] + _dispatch("(2f - 1b)", "0") + ["2:"]
     for var in range(M << M):
-        lines += fmas(var, "%[ga]", "%[gb]") + ["s_cmp_lg_u32 s78, 0", "s_cbranch_scc1 8b",
-                                                "s_branch 9f"]
+        # the next record's load is issued before the FMAs (the table is
+        # followed by readable padding), its dispatch after them
+        lines += (["s_load_dwordx8 s[80:87], s[76:77], 0x0"] + fmas(var, "%[ga]", "%[gb]") +
+                  ["s_cmp_eq_u32 s78, 0", "s_cbranch_scc1 9f", "s_waitcnt lgkmcnt(0)"] +
+                  _dispatch("(2b - 1b)", "-1"))
     lines += ["9:", "s_mov_b32 %[plo], s76", "s_mov_b32 %[phi], s77", "s_mov_b32 %[cnt], s78"]
     return lines
 

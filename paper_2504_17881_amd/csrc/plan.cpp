@@ -914,7 +914,7 @@ static prx_status plan_create_impl(const prx_sched *sched, int n, prx_dtype dtyp
         WsLayout &w = P->ws;
         w.rot_off = 0;
         w.rot_bytes = P->rot_table.size();
-        w.chunk_off = align256(w.rot_off + w.rot_bytes);
+        w.chunk_off = align256(w.rot_off + w.rot_bytes + kRecordReadAhead);
         w.chunk_bytes = P->chunks.size() * sizeof(ChunkRec);
         w.part_off = align256(w.chunk_off + w.chunk_bytes);
         w.part_bytes = maxblocks * sizeof(double);

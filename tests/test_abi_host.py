@@ -285,21 +285,27 @@ def test_rotation_jump_table_is_generated_from_its_script(tmp_path):
         dst = [x.split()[1].rstrip(",") for x in v[:32]]
         assert sorted(dst) == sorted(f"%{i}" for i in range(32))
     assert lines[0] == "s_min_u32 %32, %35, 63" and gen.VARIANT_BYTES == 260
-    # the threaded loop: same FMAs per variant, then the loop test and exits
+    # the threaded loop: each variant loads the next record, applies the same
+    # FMAs as the table's variant, tests the count and dispatches the next
+    # record itself
     with open(tmp_path / "rot_loop_f32m4.inc") as f, open(os.path.join(csrc, "rot_loop_f32m4.inc")) as g:
         assert f.read() == g.read()
     loop = gen.loop_block()
     start, end = loop.index("2:"), loop.index("9:")
     body = loop[start + 1:end]
-    assert len(body) == 64 * 35 and gen.LOOP_VARIANT_BYTES == 268
+    n = len(body) // 64
+    assert len(body) == 64 * n and gen.LOOP_VARIANT_BYTES == 380
+    dispatch = gen._dispatch("(2b - 1b)", "-1")
     for var in range(64):
-        v = body[35 * var:35 * (var + 1)]
-        assert [x.replace("%[ga]", "%33").replace("%[gb]", "%34") for x in v[:32]] == \
+        v = body[n * var:n * (var + 1)]
+        assert v[0] == "s_load_dwordx8 s[80:87], s[76:77], 0x0"
+        assert [x.replace("%[ga]", "%33").replace("%[gb]", "%34") for x in v[1:33]] == \
             gen.variant(var)[:32]
-        assert v[32:] == ["s_cmp_lg_u32 s78, 0", "s_cbranch_scc1 8b", "s_branch 9f"]
+        assert v[33:36] == ["s_cmp_eq_u32 s78, 0", "s_cbranch_scc1 9f", "s_waitcnt lgkmcnt(0)"]
+        assert v[36:] == dispatch
     # the diagonal variant index leaves before the jump; the count is tested
     # on entry and after every rotation
-    assert loop.index("s_cmp_eq_u32 s88, 64") < loop.index("s_setpc_b64 s[90:91]")
+    assert dispatch.index("s_cmp_eq_u32 s88, 64") < dispatch.index("s_setpc_b64 s[90:91]")
     assert loop[3:5] == ["s_cmp_eq_u32 s78, 0", "s_cbranch_scc1 9f"]
 
 
@@ -346,16 +352,16 @@ def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
     table starts right after s_setpc_b64 and the jump adds (table - return
     address) and stride * min(var, 63) to the return address.  In the
     jump table (stride 260) variant v is 32 eight-byte v_fma_f32 and one
-    s_branch to the table's end; in the threaded loop (stride 268) it is 32
-    v_fma_f32, the count test, a branch back to the loop header (the scalar
-    load of the next record) and a branch to the exit, and every exit of the
-    loop lands on the same address.  A different encoding size would send
+    s_branch to the table's end; in the threaded loop (stride 380) it is the
+    next record's scalar load, 32 v_fma_f32, the count test with its exit,
+    the wait and the next record's dispatch, whose computed jump returns to
+    the same table, and every exit of the loop lands on the same address.  A different encoding size would send
     the jump into the middle of an instruction."""
     ins = _code_object(tmp_path, obj_name)
     addr = [a for a, _, _ in ins]
     at = {a: i for i, a in enumerate(addr)}
     tables = [i for i, (_, op, txt) in enumerate(ins) if op == "s_setpc_b64" and "s[90:91]" in txt]
-    kinds = {260: 0, 268: 0}
+    kinds = {260: 0, 380: 0}
     for i in tables:
         # preamble: s_min_u32, s_mul_i32 stride, s_getpc_b64, s_add/addc (var),
         # s_add/addc (label offset), s_setpc_b64
@@ -365,10 +371,14 @@ def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
         assert ins[i - 7][2].endswith(", 63")
         stride = int(ins[i - 6][2].rsplit(",", 1)[1].strip(), 0)
         assert stride in kinds, stride
-        kinds[stride] += 1
         ret = addr[i - 4]                       # s_getpc_b64 yields the next address
-        start = addr[i + 1]
         off = int(ins[i - 2][2].rsplit(",", 1)[1].strip(), 0)
+        if off >= 1 << 31:
+            off -= 1 << 32
+        if stride == 380 and off < 0:
+            continue                            # a variant's dispatch (checked below)
+        kinds[stride] += 1
+        start = addr[i + 1]
         assert ret + off == start, (hex(ret), off, hex(start))
         end = start + 64 * stride
         assert end in at
@@ -382,22 +392,37 @@ def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
                 assert ins[j][1] == "s_branch" and _branch_target(ins, j) == end, (var, ins[j])
                 assert addr[j + 1] == base + 260
             continue
-        # threaded loop: the header is the record load before the jump
-        hdr = max(j for j in range(i) if ins[j][1] == "s_load_dwordx8" and "s[80:87]" in ins[j][2])
-        assert i - hdr < 40
-        exits = [j for j in range(hdr - 2, i) if ins[j][1] == "s_cbranch_scc1"]
-        assert len(exits) == 2 and all(_branch_target(ins, j) == end for j in exits)
+        # threaded loop: the header's jump starts the table; every variant
+        # is the next record's load, 32 FMAs, the count test with its exit,
+        # the wait and a dispatch whose computed jump targets the same table
+        hexits = [j for j in range(i - 30, i) if ins[j][1] == "s_cbranch_scc1"]
+        assert len(hexits) == 2 and all(_branch_target(ins, j) == end for j in hexits)
         for var in range(64):
-            base = start + 268 * var
+            base = start + 380 * var
+            j = at[base]
+            assert ins[j][1] == "s_load_dwordx8" and "s[80:87], s[76:77]" in ins[j][2], ins[j]
             for k in range(32):
-                j = at[base + 8 * k]
+                j = at[base + 8 + 8 * k]
                 assert ins[j][1] == "v_fma_f32", (var, k, ins[j])
-            j = at[base + 256]
-            assert ins[j][1] == "s_cmp_lg_u32" and ins[j][2].endswith("s78, 0"), ins[j]
-            assert ins[j + 1][1] == "s_cbranch_scc1" and _branch_target(ins, j + 1) == addr[hdr]
-            assert ins[j + 2][1] == "s_branch" and _branch_target(ins, j + 2) == end
-            assert addr[j + 3] == base + 268
-    assert kinds[268] >= 1, "no threaded rotation loop in the code object"
+            j = at[base + 264]
+            assert ins[j][1] == "s_cmp_eq_u32" and ins[j][2].endswith("s78, 0"), ins[j]
+            assert ins[j + 1][1] == "s_cbranch_scc1" and _branch_target(ins, j + 1) == end
+            assert ins[j + 2][1] == "s_waitcnt"
+            assert [op for _, op, _ in ins[j + 3:j + 6]] == ["s_bfe_u32", "s_cmp_eq_u32",
+                                                          "s_cbranch_scc1"]
+            assert _branch_target(ins, j + 5) == end          # diagonal record: exit
+            k = j + 22
+            assert [op for _, op, _ in ins[k - 7:k + 1]] == [
+                "s_min_u32", "s_mul_i32", "s_getpc_b64", "s_add_u32", "s_addc_u32", "s_add_u32",
+                "s_addc_u32", "s_setpc_b64"]
+            assert ins[k - 7][2].endswith(", 63")
+            assert int(ins[k - 6][2].rsplit(",", 1)[1].strip(), 0) == 380
+            o2 = int(ins[k - 2][2].rsplit(",", 1)[1].strip(), 0)
+            if o2 >= 1 << 31:
+                o2 -= 1 << 32
+            assert addr[k - 4] + o2 == start and ins[k - 1][2].endswith("-1")
+            assert addr[k + 1] == base + 380
+    assert kinds[380] >= 1, "no threaded rotation loop in the code object"
     if obj_name == "kernels.hip.o":
         assert kinds[260] >= 1, "no jump table in the code object"
 
