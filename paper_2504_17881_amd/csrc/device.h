@@ -335,17 +335,21 @@ __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t
         while (true) {
             rot_loop(amp, k0, tbase, plo, phi, cnt);
             if (cnt == 0u) break;
-            const RotRec<T> *rp =
-                reinterpret_cast<const RotRec<T> *>(((uint64_t)phi << 32) | plo);
-            const RotRec<T> rec = *rp;
-            const uint32_t zeta = (rec.info >> 8) & 0xffu;
+            // the record's fields through the constant address space (scalar
+            // loads: the pointer is uniform)
+            typedef const __attribute__((address_space(4))) RotRec<T> *ConstRec;
+            const ConstRec rp = (ConstRec)((((uint64_t)phi) << 32) | plo);
+            const uint64_t rz = rp->z, rzhigh = rp->zhigh;
+            const uint32_t info = rp->info;
+            const T tau_a = rp->tau_a;
+            const uint32_t zeta = (info >> 8) & 0xffu;
             const uint32_t tpar =
-                __builtin_amdgcn_readfirstlane((uint32_t)__builtin_popcountll(tbase & rec.zhigh));
+                __builtin_amdgcn_readfirstlane((uint32_t)__builtin_popcountll(tbase & rzhigh));
             uint32_t c, ua;
-            asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(c) : "v"(k0 & (uint32_t)rec.z), "s"(tpar));
+            asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(c) : "v"(k0 & (uint32_t)rz), "s"(tpar));
             asm("v_lshl_add_u32 %0, %1, 31, %2"
                 : "=v"(ua)
-                : "v"(c), "s"(__builtin_amdgcn_readfirstlane(__float_as_uint(rec.tau_a))));
+                : "v"(c), "s"(__builtin_amdgcn_readfirstlane(__float_as_uint(tau_a))));
             rot_diag<T, M>(amp, __uint_as_float(ua), zeta);
             const uint64_t pn = (((uint64_t)phi << 32) | plo) + sizeof(RotRec<T>);
             plo = (uint32_t)pn;
