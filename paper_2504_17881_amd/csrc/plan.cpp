@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -736,6 +737,13 @@ static void apply_opts(const prx_plan_opts *o, PlanCfg &c) {
     if (o->max_grid > 0)
         c.grid_cap = (unsigned)std::min<uint64_t>((uint64_t)o->max_grid, kMaxGridBlocks);
 }
+
+// The threaded rotation loop of the complex64 tile chunks reads one record
+// with one 32-byte scalar load: z, zhigh, info, pad, tau_a, tau_b.
+static_assert(sizeof(RotRec<float>) == 32 && offsetof(RotRec<float>, zhigh) == 8 &&
+                  offsetof(RotRec<float>, info) == 16 && offsetof(RotRec<float>, tau_a) == 24 &&
+                  offsetof(RotRec<float>, tau_b) == 28,
+              "record layout read by the threaded rotation loop");
 
 template <typename T>
 static void pack_records(prx_plan &P, const std::vector<RotRecD> &recs) {

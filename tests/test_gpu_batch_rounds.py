@@ -99,6 +99,51 @@ def test_tile_rounds_with_many_virtual_qubits(dtype):
     _free(hams, scheds)
 
 
+@pytest.mark.parametrize("dtype", [P.PRX_C64, P.PRX_C128])
+def test_tile_rounds_with_diagonal_terms(dtype):
+    """Hamiltonians with Z-only terms: the qDRIFT draws put diagonal
+    rotations inside the tile rounds' chunks (at complex64 the threaded
+    rotation loop stops at each one and resumes after it)."""
+    ns = [13, 16, 12]
+    N = 400
+    hams, scheds = {}, []
+    rng = np.random.default_rng(61)
+    for i, n in enumerate(ns):
+        x, z, h = synth.jw_hamiltonian(n, 100, 500 + n)
+        zs = set()
+        while len(zs) < 40:
+            zs.add(int(rng.integers(1, 1 << n)))
+        x = np.concatenate([np.asarray(x, dtype=np.uint64), np.zeros(40, dtype=np.uint64)])
+        z = np.concatenate([np.asarray(z, dtype=np.uint64), np.array(sorted(zs), dtype=np.uint64)])
+        h = np.concatenate([np.asarray(h, dtype=np.float64), rng.normal(0.0, 0.5, size=40)])
+        hams[n] = (x, z, h, P.prx_ham_create(n, x, z, h))
+        scheds.append(P.prx_sched_qdrift(hams[n][3], 0.7, N, 90 + i))
+    basis = [synth.basis_index(n) for n in ns]
+    psis = [basis_state(n, b0, dtype) for n, b0 in zip(ns, basis)]
+    b = P.prx_batch_create(ns, scheds, dtype, basis)
+    assert P.prx_batch_get_info(b)["tile_samples"] == len(ns)
+    ws = workspace(P.prx_batch_workspace_bytes(b))
+    ovd = torch.zeros(2 * len(ns), dtype=torch.float64, device=dev())
+    P.prx_batch_upload(b, psis, ws)
+    print(f"[diagonal terms dtype={dtype}] launching", flush=True)
+    P.prx_batch_execute(b, ws, ovd)
+    P.prx_batch_check(b, ws)
+    print(f"[diagonal terms dtype={dtype}] done", flush=True)
+    tol = 1e-12 if dtype == P.PRX_C128 else 8 * EPS32 * math.sqrt(N) + 1e-6
+    ndiag = 0
+    for i, n in enumerate(ns):
+        x, z, h, _ = hams[n]
+        rx, rz, rp = S.qdrift(x, z, h, 0.7, N, 90 + i)
+        ndiag += int(np.sum(np.asarray(rx) == 0))
+        psi0 = np.zeros(1 << n, dtype=np.complex128)
+        psi0[basis[i]] = 1
+        ref = sv.c_apply_rotations(psi0, rx, rz, rp)
+        assert rel_err(to_host(psis[i]), ref) <= tol, (i, n)
+    assert ndiag >= 30
+    P.prx_batch_destroy(b)
+    _free(hams, scheds)
+
+
 @pytest.mark.parametrize("dtype", [P.PRX_C128, P.PRX_C64])
 def test_capped_round_grids_stride_over_the_items(dtype):
     """With every round launch capped at 3 workgroups, both round kernels

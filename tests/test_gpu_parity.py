@@ -166,6 +166,45 @@ def test_diagonal_identity_and_large_angles():
         assert rel_err(to_host(t), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("B", [12, 14])
+def test_diagonal_records_inside_complex64_tile_chunks(B):
+    """Z-only rotations interleaved with others (alone, in runs of three,
+    first or last in a chunk) inside complex64 tile chunks, where the
+    threaded rotation loop stops at each diagonal record, leaves it to the
+    compiled path and resumes after it; 12-qubit tile-sets (five workgroups
+    per CU) and the persistent 14-qubit ones."""
+    n, M = 17, 600
+    rng = np.random.default_rng(40 + B)
+    x = np.array([int(v) for v in rng.integers(1, 1 << n, size=M)], dtype=np.uint64)
+    z = np.array([int(v) for v in rng.integers(0, 1 << n, size=M)], dtype=np.uint64)
+    phi = rng.uniform(-math.pi, math.pi, size=M)
+    for i in range(M):
+        if i % 5 == 0 or i % 37 in (1, 2, 3):
+            x[i] = 0
+    opts = dict(tile_qubits=B, chunk_rank=4, max_virtual=B - 4, tile_only=1)
+    s = P.prx_sched_from_rotations(n, x, z, phi)
+    pl = P.prx_plan_create(s, n, P.PRX_C64, 0, M, P.PRX_FUSED, opts)
+    first = last = inner = 0
+    for i in range(P.prx_plan_get_info(pl)["passes"]):
+        ps = P.prx_plan_pass(pl, i)
+        assert ps["kind"] == 2
+        for c in range(ps["chunk_begin"], ps["chunk_begin"] + ps["chunk_count"]):
+            ch = P.prx_plan_chunk(pl, c)
+            d = [P.prx_plan_rotation(pl, ch["rot_begin"] + j)["var"] == 64
+                 for j in range(ch["rot_count"])]
+            first += d[0]
+            last += d[-1]
+            inner += any(d[j] and d[j + 1] for j in range(1, len(d) - 2))
+    P.prx_plan_destroy(pl)
+    P.prx_sched_destroy(s)
+    assert first >= 1 and last >= 10 and inner >= 10, (first, last, inner)
+    psi0 = synth.gaussian_state(n, 41)
+    ref = sv.c_apply_rotations(psi0, x, z, phi)
+    print(f"[diagonal records B={B}]", flush=True)
+    t, info = _run_both(n, x, z, phi, psi0, P.PRX_C64, P.PRX_FUSED, opts)
+    assert rel_err(to_host(t), ref) <= c64_tol(M), info
+
+
 def test_empty_range_is_noop():
     n = 10
     x, z, phi = synth.random_pauli_rotations(n, 5, seed=1)
