@@ -266,6 +266,25 @@ __device__ __forceinline__ void rot_jump(Cx<float> (&amp)[16], float ga, float g
         : "s90", "s91", "scc");
 }
 
+// The complex128 variants as the same kind of table (rot_jump_f64m4.inc).
+#include "rot_jump_f64m4.inc"
+__device__ __forceinline__ void rot_jump(Cx<double> (&amp)[16], double ga, double gb,
+                                         uint32_t var) {
+    uint32_t t;
+    asm(PRX_ROT_JUMP_F64M4
+        : "+v"(amp[0].re), "+v"(amp[0].im), "+v"(amp[1].re), "+v"(amp[1].im),
+          "+v"(amp[2].re), "+v"(amp[2].im), "+v"(amp[3].re), "+v"(amp[3].im),
+          "+v"(amp[4].re), "+v"(amp[4].im), "+v"(amp[5].re), "+v"(amp[5].im),
+          "+v"(amp[6].re), "+v"(amp[6].im), "+v"(amp[7].re), "+v"(amp[7].im),
+          "+v"(amp[8].re), "+v"(amp[8].im), "+v"(amp[9].re), "+v"(amp[9].im),
+          "+v"(amp[10].re), "+v"(amp[10].im), "+v"(amp[11].re), "+v"(amp[11].im),
+          "+v"(amp[12].re), "+v"(amp[12].im), "+v"(amp[13].re), "+v"(amp[13].im),
+          "+v"(amp[14].re), "+v"(amp[14].im), "+v"(amp[15].re), "+v"(amp[15].im),
+          "=&s"(t)
+        : "v"(ga), "v"(gb), "s"(__builtin_amdgcn_readfirstlane(var))
+        : "s90", "s91", "scc");
+}
+
 // Binary dispatch of a static-sign rotation on the uniform variant index
 // var = slot 2^M + imag 2^(M-1) + zp in [LO, HI); var = M 2^M is the
 // diagonal (x = 0) rotation.
@@ -390,7 +409,7 @@ __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t
                 gb = pin(flip_add(rec.tau_b, cnt));
             }
             const uint32_t var = (rec.info >> 16) & 0xffu;
-            if constexpr (sizeof(T) == 4 && M == 4) {
+            if constexpr (M == 4) {
                 if (var == (uint32_t)(M << M))
                     rot_diag<T, M>(amp, ga, zeta);
                 else

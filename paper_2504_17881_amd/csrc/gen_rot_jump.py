@@ -13,7 +13,8 @@ its table instead of walking a branch tree.
 
 Operands of the generated block: %0..%31 the amplitudes (re, im of amp[0],
 amp[1], ...), %32 a scratch SGPR, %33 ga, %34 gb, %35 var; it clobbers
-s[90:91] and SCC.
+s[90:91] and SCC.  rot_jump_f64m4.inc is the same table for complex128:
+the same layout with v_fma_f64 on register pairs (also 8 bytes each).
 
 It also writes rot_loop_f32m4.inc: a whole run of rotations of a tile
 chunk as one block of threaded code.  A header loads the first 32-byte
@@ -44,39 +45,39 @@ def drop_bit(v, i):
     return ((v >> (i + 1)) << i) | (v & ((1 << i) - 1))
 
 
-def pair(v, w, imag, neg, ga="%33", gb="%34"):
+def pair(v, w, imag, neg, ga="%33", gb="%34", op="v_fma_f32"):
     ar, ai, br, bi = f"%{2 * v}", f"%{2 * v + 1}", f"%{2 * w}", f"%{2 * w + 1}"
     n = "-" if neg else ""
     p = "" if neg else "-"
     if not imag:
-        return [f"v_fma_f32 {ar}, {n}{ga}, {br}, {ar}",
-                f"v_fma_f32 {ai}, {n}{ga}, {bi}, {ai}",
-                f"v_fma_f32 {br}, {n}{gb}, {ar}, {br}",
-                f"v_fma_f32 {bi}, {n}{gb}, {ai}, {bi}"]
+        return [f"{op} {ar}, {n}{ga}, {br}, {ar}",
+                f"{op} {ai}, {n}{ga}, {bi}, {ai}",
+                f"{op} {br}, {n}{gb}, {ar}, {br}",
+                f"{op} {bi}, {n}{gb}, {ai}, {bi}"]
     # a <- a + i ga b, b <- b + i gb a (negated coefficients when neg)
-    return [f"v_fma_f32 {ar}, {p}{ga}, {bi}, {ar}",
-            f"v_fma_f32 {ai}, {n}{ga}, {br}, {ai}",
-            f"v_fma_f32 {br}, {p}{gb}, {ai}, {br}",
-            f"v_fma_f32 {bi}, {n}{gb}, {ar}, {bi}"]
+    return [f"{op} {ar}, {p}{ga}, {bi}, {ar}",
+            f"{op} {ai}, {n}{ga}, {br}, {ai}",
+            f"{op} {br}, {p}{gb}, {ai}, {br}",
+            f"{op} {bi}, {n}{gb}, {ar}, {bi}"]
 
 
-def fmas(var, ga="%33", gb="%34"):
+def fmas(var, ga="%33", gb="%34", op="v_fma_f32"):
     slot, imag, zp = var >> M, (var >> (M - 1)) & 1, var & ((1 << (M - 1)) - 1)
     out = []
     for v in range(1 << M):
         if v >> slot & 1:
             continue
         neg = bin(drop_bit(v, slot) & zp).count("1") & 1
-        out += pair(v, v | (1 << slot), imag, neg, ga, gb)
+        out += pair(v, v | (1 << slot), imag, neg, ga, gb, op)
     assert len(out) == 32
     return out
 
 
-def variant(var):
-    return fmas(var) + ["s_branch 3f"]
+def variant(var, op="v_fma_f32"):
+    return fmas(var, op=op) + ["s_branch 3f"]
 
 
-def block():
+def block(op="v_fma_f32"):
     lines = ["s_min_u32 %32, %35, 63",
              f"s_mul_i32 %32, %32, {VARIANT_BYTES}",
              "s_getpc_b64 s[90:91]",
@@ -88,7 +89,7 @@ def block():
              "s_setpc_b64 s[90:91]",
              "2:"]
     for var in range(M << M):
-        lines += variant(var)
+        lines += variant(var, op)
     lines.append("3:")
     return lines
 
@@ -148,6 +149,15 @@ def main():
             "#define PRX_ROT_JUMP_F32M4 \\\n" + " \\\n".join(
                 f'    "{line}\\n"' for line in block()) + "\n")
     with open(os.path.join(here, "rot_jump_f32m4.inc"), "w") as f:
+        f.write(text)
+    text = ("// Generated by gen_rot_jump.py; do not edit.\n"
+            "// Jump table of the 64 complex128 rank-4 static-sign rotation variants\n"
+            "// (v_fma_f64 on register pairs; operands and layout as the complex64\n"
+            "// table: see gen_rot_jump.py).\n"
+            "#pragma once\n"
+            "#define PRX_ROT_JUMP_F64M4 \\\n" + " \\\n".join(
+                f'    "{line}\\n"' for line in block("v_fma_f64")) + "\n")
+    with open(os.path.join(here, "rot_jump_f64m4.inc"), "w") as f:
         f.write(text)
     text = ("// Generated by gen_rot_jump.py; do not edit.\n"
             "// Threaded rotation loop over the 64 complex64 rank-4 static-sign\n"

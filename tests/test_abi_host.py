@@ -272,8 +272,11 @@ def test_rotation_jump_table_is_generated_from_its_script(tmp_path):
     gen = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(gen)
     gen.main()
-    with open(tmp_path / "rot_jump_f32m4.inc") as f, open(os.path.join(csrc, "rot_jump_f32m4.inc")) as g:
-        assert f.read() == g.read()
+    for inc in ("rot_jump_f32m4.inc", "rot_jump_f64m4.inc"):
+        with open(tmp_path / inc) as f, open(os.path.join(csrc, inc)) as g:
+            assert f.read() == g.read(), inc
+    f64 = gen.block("v_fma_f64")
+    assert [x.replace("v_fma_f64", "v_fma_f32") for x in f64] == gen.block()
     lines = gen.block()
     start, end = lines.index("2:"), lines.index("3:")
     body = lines[start + 1:end]
@@ -383,11 +386,14 @@ def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
         end = start + 64 * stride
         assert end in at
         if stride == 260:
+            fma = ins[at[start]][1]             # complex64 or complex128 table
+            assert fma in ("v_fma_f32", "v_fma_f64"), ins[at[start]]
+            kinds[fma] = kinds.get(fma, 0) + 1
             for var in range(64):
                 base = start + 260 * var
                 for k in range(32):
                     j = at[base + 8 * k]
-                    assert ins[j][1] == "v_fma_f32", (var, k, ins[j])
+                    assert ins[j][1] == fma, (var, k, ins[j])
                 j = at[base + 256]
                 assert ins[j][1] == "s_branch" and _branch_target(ins, j) == end, (var, ins[j])
                 assert addr[j + 1] == base + 260
@@ -424,7 +430,7 @@ def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
             assert addr[k + 1] == base + 380
     assert kinds[380] >= 1, "no threaded rotation loop in the code object"
     if obj_name == "kernels.hip.o":
-        assert kinds[260] >= 1, "no jump table in the code object"
+        assert kinds.get("v_fma_f32", 0) >= 1 and kinds.get("v_fma_f64", 0) >= 1, kinds
 
 
 def test_launch_grids_stay_inside_the_work_item_range():
