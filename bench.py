@@ -59,7 +59,7 @@ def kernel_symbol(ps: dict, dtype_name: str) -> str:
 def kernel_sources_digest() -> str:
     h = hashlib.sha256()
     for f in ("kernels.hip", "device.h", "internal.h", "rot_jump_f32m4.inc",
-              "rot_loop_f32m4.inc"):
+              "rot_loop_f32m4.inc", "rot_jump_f64m4.inc", "rot_loop_f64m4.inc"):
         with open(os.path.join(ROOT, "paper_2504_17881_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -341,10 +341,34 @@ __device__ __forceinline__ void rot_loop(Cx<float> (&amp)[16], uint32_t k0, uint
     cnt = __builtin_amdgcn_readfirstlane(cnt);
 }
 
+#include "rot_loop_f64m4.inc"
+__device__ __forceinline__ void rot_loop(Cx<double> (&amp)[16], uint32_t k0, uint64_t tb,
+                                         uint32_t &plo, uint32_t &phi, uint32_t &cnt) {
+    double ga, gb, sg;
+    uint32_t t;
+    asm volatile(PRX_ROT_LOOP_F64M4
+        : "+v"(amp[0].re), "+v"(amp[0].im), "+v"(amp[1].re), "+v"(amp[1].im),
+          "+v"(amp[2].re), "+v"(amp[2].im), "+v"(amp[3].re), "+v"(amp[3].im),
+          "+v"(amp[4].re), "+v"(amp[4].im), "+v"(amp[5].re), "+v"(amp[5].im),
+          "+v"(amp[6].re), "+v"(amp[6].im), "+v"(amp[7].re), "+v"(amp[7].im),
+          "+v"(amp[8].re), "+v"(amp[8].im), "+v"(amp[9].re), "+v"(amp[9].im),
+          "+v"(amp[10].re), "+v"(amp[10].im), "+v"(amp[11].re), "+v"(amp[11].im),
+          "+v"(amp[12].re), "+v"(amp[12].im), "+v"(amp[13].re), "+v"(amp[13].im),
+          "+v"(amp[14].re), "+v"(amp[14].im), "+v"(amp[15].re), "+v"(amp[15].im),
+          [plo] "+s"(plo), [phi] "+s"(phi), [cnt] "+s"(cnt), [ga] "=&v"(ga), [gb] "=&v"(gb),
+          [sg] "=&v"(sg), [t] "=&v"(t)
+        : [k0] "v"(k0), [tb] "s"(tb)
+        : "s76", "s77", "s78", "s79", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87",
+          "s88", "s89", "s90", "s91", "s92", "s93", "scc", "memory");
+    plo = __builtin_amdgcn_readfirstlane(plo);
+    phi = __builtin_amdgcn_readfirstlane(phi);
+    cnt = __builtin_amdgcn_readfirstlane(cnt);
+}
+
 template <typename T, int M, typename K0>
 __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t tbase,
                                            const RotRec<T> *__restrict__ rots, uint32_t count) {
-    if constexpr (sizeof(T) == 4 && M == 4 && sizeof(K0) == 4) {
+    if constexpr (M == 4 && sizeof(K0) == 4) {
         // tile chunks at complex64: the threaded loop, stopping for the
         // diagonal records, which take the compiled path below
         const uint64_t p0 = (uint64_t)rots;
@@ -364,12 +388,17 @@ __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t
             const uint32_t zeta = (info >> 8) & 0xffu;
             const uint32_t tpar =
                 __builtin_amdgcn_readfirstlane((uint32_t)__builtin_popcountll(tbase & rzhigh));
-            uint32_t c, ua;
+            uint32_t c;
             asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(c) : "v"(k0 & (uint32_t)rz), "s"(tpar));
-            asm("v_lshl_add_u32 %0, %1, 31, %2"
-                : "=v"(ua)
-                : "v"(c), "s"(__builtin_amdgcn_readfirstlane(__float_as_uint(tau_a))));
-            rot_diag<T, M>(amp, __uint_as_float(ua), zeta);
+            if constexpr (sizeof(T) == 4) {
+                uint32_t ua;
+                asm("v_lshl_add_u32 %0, %1, 31, %2"
+                    : "=v"(ua)
+                    : "v"(c), "s"(__builtin_amdgcn_readfirstlane(__float_as_uint(tau_a))));
+                rot_diag<T, M>(amp, __uint_as_float(ua), zeta);
+            } else {
+                rot_diag<T, M>(amp, pin(flip_add(tau_a, c)), zeta);
+            }
             const uint64_t pn = (((uint64_t)phi << 32) | plo) + sizeof(RotRec<T>);
             plo = (uint32_t)pn;
             phi = (uint32_t)(pn >> 32);

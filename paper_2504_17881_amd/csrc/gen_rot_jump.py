@@ -32,6 +32,14 @@ record pointer and %[cnt] the records left (read and written), %[ga], %[gb]
 scratch, %[k0] the lane's coset representative, %[tb] the base tile index;
 it clobbers s[76:91] and SCC.
 
+rot_loop_f64m4.inc is the threaded loop for complex128: 40-byte records
+(tau_b at byte 32, loaded into s[92:93]), v_fma_f64 on register pairs, and
+the lane's sign applied as a factor of +-1.0 (v_cvt_f64_i32 of 1 - 2 parity)
+by two v_mul_f64, since the high word of a register pair operand cannot be
+named on its own; variants are 404 bytes and the table must be followed by
+40 readable bytes.  Extra operands: %[sg] (a register pair) and %[t]
+scratch; it also clobbers s[92:93].
+
 Run from this directory: python3 gen_rot_jump.py
 """
 import os
@@ -139,6 +147,52 @@ def loop_block():
     return lines
 
 
+# complex128: 40-byte records (tau_b at byte 32 in s[92:93]); the lane sign
+# becomes a factor of +-1.0 that multiplies both coefficients
+LOOP64_VARIANT_BYTES = 404
+
+
+def _dispatch64(off, hi):
+    return ["s_bfe_u32 s88, s84, 0x80010",
+            "s_cmp_eq_u32 s88, 64",
+            "s_cbranch_scc1 9f",
+            "s_and_b64 s[82:83], s[82:83], %[tb]",
+            "s_bcnt1_i32_b64 s89, s[82:83]",
+            "v_and_b32 %[t], s80, %[k0]",
+            "v_bcnt_u32_b32 %[t], %[t], s89",
+            "v_and_b32 %[t], 1, %[t]",
+            "v_mad_i32_i24 %[t], %[t], -2, 1",     # 1 - 2 parity
+            "v_cvt_f64_i32 %[sg], %[t]",
+            "v_mul_f64 %[ga], %[sg], s[86:87]",
+            "v_mul_f64 %[gb], %[sg], s[92:93]",
+            "s_add_u32 s76, s76, 40",
+            "s_addc_u32 s77, s77, 0",
+            "s_sub_u32 s78, s78, 1",
+            "s_min_u32 s88, s88, 63",
+            f"s_mul_i32 s88, s88, {LOOP64_VARIANT_BYTES}",
+            "s_getpc_b64 s[90:91]",
+            "1:",
+            "s_add_u32 s90, s90, s88",
+            "s_addc_u32 s91, s91, 0",
+            f"s_add_u32 s90, s90, {off}",
+            f"s_addc_u32 s91, s91, {hi}",
+            "s_setpc_b64 s[90:91]"]
+
+
+def loop_block64():
+    loads = ["s_load_dwordx8 s[80:87], s[76:77], 0x0",
+             "s_load_dwordx2 s[92:93], s[76:77], 0x20"]
+    lines = (["s_mov_b32 s76, %[plo]", "s_mov_b32 s77, %[phi]", "s_mov_b32 s78, %[cnt]",
+              "s_cmp_eq_u32 s78, 0", "s_cbranch_scc1 9f"] + loads +
+             ["s_waitcnt lgkmcnt(0)"] + _dispatch64("(2f - 1b)", "0") + ["2:"])
+    for var in range(M << M):
+        lines += (loads + fmas(var, "%[ga]", "%[gb]", "v_fma_f64") +
+                  ["s_cmp_eq_u32 s78, 0", "s_cbranch_scc1 9f", "s_waitcnt lgkmcnt(0)"] +
+                  _dispatch64("(2b - 1b)", "-1"))
+    lines += ["9:", "s_mov_b32 %[plo], s76", "s_mov_b32 %[phi], s77", "s_mov_b32 %[cnt], s78"]
+    return lines
+
+
 def main():
     here = os.path.dirname(os.path.abspath(__file__))
     text = ("// Generated by gen_rot_jump.py; do not edit.\n"
@@ -167,6 +221,15 @@ def main():
             "#define PRX_ROT_LOOP_F32M4 \\\n" + " \\\n".join(
                 f'    "{line}\\n"' for line in loop_block()) + "\n")
     with open(os.path.join(here, "rot_loop_f32m4.inc"), "w") as f:
+        f.write(text)
+    text = ("// Generated by gen_rot_jump.py; do not edit.\n"
+            "// Threaded rotation loop over the 64 complex128 rank-4 static-sign\n"
+            "// variants (operands and layout: see gen_rot_jump.py).\n"
+            "#pragma once\n"
+            f"#define PRX_ROT_LOOP64_VARIANT_BYTES {LOOP64_VARIANT_BYTES}\n"
+            "#define PRX_ROT_LOOP_F64M4 \\\n" + " \\\n".join(
+                f'    "{line}\\n"' for line in loop_block64()) + "\n")
+    with open(os.path.join(here, "rot_loop_f64m4.inc"), "w") as f:
         f.write(text)
 
 

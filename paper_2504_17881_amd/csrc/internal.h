@@ -74,9 +74,10 @@ static constexpr int kMaxChunkRank = 6;
 // and at least 16 contiguous amplitudes per tile (128 B at complex64).
 static constexpr int kMaxVirtual = 10;
 static constexpr int kMinTileLow = 4;
-// Readable bytes after a rotation table: the threaded rotation loop loads
-// the record after the current one before it knows whether one follows.
-static constexpr size_t kRecordReadAhead = 32;
+// Readable bytes after a rotation table: the threaded rotation loops load
+// the record after the current one (32 bytes at complex64, 40 at
+// complex128) before they know whether one follows.
+static constexpr size_t kRecordReadAhead = 64;
 
 // Most threads of a tile workgroup (2^(B - m) <= 2^10).
 static constexpr int kMaxTileThreadBits = 10;

@@ -744,6 +744,11 @@ static_assert(sizeof(RotRec<float>) == 32 && offsetof(RotRec<float>, zhigh) == 8
                   offsetof(RotRec<float>, info) == 16 && offsetof(RotRec<float>, tau_a) == 24 &&
                   offsetof(RotRec<float>, tau_b) == 28,
               "record layout read by the threaded rotation loop");
+// The complex128 loop reads 32 bytes (z, zhigh, info, pad, tau_a) and then
+// tau_b at byte 32.
+static_assert(sizeof(RotRec<double>) == 40 && offsetof(RotRec<double>, info) == 16 &&
+                  offsetof(RotRec<double>, tau_a) == 24 && offsetof(RotRec<double>, tau_b) == 32,
+              "record layout read by the complex128 threaded rotation loop");
 
 template <typename T>
 static void pack_records(prx_plan &P, const std::vector<RotRecD> &recs) {

@@ -310,6 +310,23 @@ def test_rotation_jump_table_is_generated_from_its_script(tmp_path):
     # on entry and after every rotation
     assert dispatch.index("s_cmp_eq_u32 s88, 64") < dispatch.index("s_setpc_b64 s[90:91]")
     assert loop[3:5] == ["s_cmp_eq_u32 s78, 0", "s_cbranch_scc1 9f"]
+    # the complex128 loop: same structure with both record loads and f64 FMAs
+    with open(tmp_path / "rot_loop_f64m4.inc") as f, open(os.path.join(csrc, "rot_loop_f64m4.inc")) as g:
+        assert f.read() == g.read()
+    loop = gen.loop_block64()
+    body = loop[loop.index("2:") + 1:loop.index("9:")]
+    n = len(body) // 64
+    assert len(body) == 64 * n and gen.LOOP64_VARIANT_BYTES == 404
+    dispatch = gen._dispatch64("(2b - 1b)", "-1")
+    for var in range(64):
+        v = body[n * var:n * (var + 1)]
+        assert v[:2] == ["s_load_dwordx8 s[80:87], s[76:77], 0x0",
+                         "s_load_dwordx2 s[92:93], s[76:77], 0x20"]
+        assert [x.replace("%[ga]", "%33").replace("%[gb]", "%34") for x in v[2:34]] == \
+            gen.variant(var, "v_fma_f64")[:32]
+        assert v[34:37] == ["s_cmp_eq_u32 s78, 0", "s_cbranch_scc1 9f", "s_waitcnt lgkmcnt(0)"]
+        assert v[37:] == dispatch
+    assert "s_add_u32 s76, s76, 40" in dispatch
 
 
 def _code_object(tmp_path, obj_name):
@@ -355,16 +372,17 @@ def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
     table starts right after s_setpc_b64 and the jump adds (table - return
     address) and stride * min(var, 63) to the return address.  In the
     jump table (stride 260) variant v is 32 eight-byte v_fma_f32 and one
-    s_branch to the table's end; in the threaded loop (stride 380) it is the
-    next record's scalar load, 32 v_fma_f32, the count test with its exit,
-    the wait and the next record's dispatch, whose computed jump returns to
-    the same table, and every exit of the loop lands on the same address.  A different encoding size would send
+    s_branch to the table's end; in the threaded loops (stride 380 at
+    complex64, 404 at complex128) it is the next record's scalar load(s),
+    32 FMAs, the count test with its exit, the wait and the next record's
+    dispatch, whose computed jump returns to the same table, and every exit
+    of the loop lands on the same address.  A different encoding size would send
     the jump into the middle of an instruction."""
     ins = _code_object(tmp_path, obj_name)
     addr = [a for a, _, _ in ins]
     at = {a: i for i, a in enumerate(addr)}
     tables = [i for i, (_, op, txt) in enumerate(ins) if op == "s_setpc_b64" and "s[90:91]" in txt]
-    kinds = {260: 0, 380: 0}
+    kinds = {260: 0, 380: 0, 404: 0}
     for i in tables:
         # preamble: s_min_u32, s_mul_i32 stride, s_getpc_b64, s_add/addc (var),
         # s_add/addc (label offset), s_setpc_b64
@@ -378,7 +396,7 @@ def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
         off = int(ins[i - 2][2].rsplit(",", 1)[1].strip(), 0)
         if off >= 1 << 31:
             off -= 1 << 32
-        if stride == 380 and off < 0:
+        if stride in (380, 404) and off < 0:
             continue                            # a variant's dispatch (checked below)
         kinds[stride] += 1
         start = addr[i + 1]
@@ -399,36 +417,41 @@ def test_rotation_jump_table_layout_in_built_code(tmp_path, obj_name):
                 assert addr[j + 1] == base + 260
             continue
         # threaded loop: the header's jump starts the table; every variant
-        # is the next record's load, 32 FMAs, the count test with its exit,
-        # the wait and a dispatch whose computed jump targets the same table
-        hexits = [j for j in range(i - 30, i) if ins[j][1] == "s_cbranch_scc1"]
+        # is the next record's load(s), 32 FMAs, the count test with its
+        # exit, the wait and a dispatch whose computed jump targets the same
+        # table (complex64: stride 380, one load; complex128: 404, two)
+        f64 = stride == 404
+        hexits = [j for j in range(i - 40, i) if ins[j][1] == "s_cbranch_scc1"]
         assert len(hexits) == 2 and all(_branch_target(ins, j) == end for j in hexits)
+        lead = 16 if f64 else 8
         for var in range(64):
-            base = start + 380 * var
+            base = start + stride * var
             j = at[base]
             assert ins[j][1] == "s_load_dwordx8" and "s[80:87], s[76:77]" in ins[j][2], ins[j]
+            if f64:
+                assert ins[j + 1][1] == "s_load_dwordx2" and "s[92:93], s[76:77], 0x20" in ins[j + 1][2]
             for k in range(32):
-                j = at[base + 8 + 8 * k]
-                assert ins[j][1] == "v_fma_f32", (var, k, ins[j])
-            j = at[base + 264]
+                j = at[base + lead + 8 * k]
+                assert ins[j][1] == ("v_fma_f64" if f64 else "v_fma_f32"), (var, k, ins[j])
+            j = at[base + lead + 256]
             assert ins[j][1] == "s_cmp_eq_u32" and ins[j][2].endswith("s78, 0"), ins[j]
             assert ins[j + 1][1] == "s_cbranch_scc1" and _branch_target(ins, j + 1) == end
             assert ins[j + 2][1] == "s_waitcnt"
             assert [op for _, op, _ in ins[j + 3:j + 6]] == ["s_bfe_u32", "s_cmp_eq_u32",
                                                           "s_cbranch_scc1"]
             assert _branch_target(ins, j + 5) == end          # diagonal record: exit
-            k = j + 22
+            k = j + (25 if f64 else 22)
             assert [op for _, op, _ in ins[k - 7:k + 1]] == [
                 "s_min_u32", "s_mul_i32", "s_getpc_b64", "s_add_u32", "s_addc_u32", "s_add_u32",
                 "s_addc_u32", "s_setpc_b64"]
             assert ins[k - 7][2].endswith(", 63")
-            assert int(ins[k - 6][2].rsplit(",", 1)[1].strip(), 0) == 380
+            assert int(ins[k - 6][2].rsplit(",", 1)[1].strip(), 0) == stride
             o2 = int(ins[k - 2][2].rsplit(",", 1)[1].strip(), 0)
             if o2 >= 1 << 31:
                 o2 -= 1 << 32
             assert addr[k - 4] + o2 == start and ins[k - 1][2].endswith("-1")
-            assert addr[k + 1] == base + 380
-    assert kinds[380] >= 1, "no threaded rotation loop in the code object"
+            assert addr[k + 1] == base + stride
+    assert kinds[380] >= 1 and kinds[404] >= 1, kinds
     if obj_name == "kernels.hip.o":
         assert kinds.get("v_fma_f32", 0) >= 1 and kinds.get("v_fma_f64", 0) >= 1, kinds
 
