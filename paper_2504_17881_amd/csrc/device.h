@@ -309,10 +309,6 @@ __device__ __forceinline__ void rot_var(Cx<T> (&amp)[1 << M], T ga, T gb, uint32
     }
 }
 
-// Applies rotations [0, count) of `rots` to the thread's coset.
-// k0: coset representative in the frame of rec.z (32-bit in a tile frame);
-// tbase: the tile index whose parity with rec.zhigh adds to the sign (0 for
-// span passes).
 // The same variants as threaded code (rot_loop_f32m4.inc): runs the records
 // at plo:phi until cnt reaches zero or a diagonal record comes up (left
 // unconsumed); k0 is the lane's coset representative, tb the base tile
@@ -341,6 +337,8 @@ __device__ __forceinline__ void rot_loop(Cx<float> (&amp)[16], uint32_t k0, uint
     cnt = __builtin_amdgcn_readfirstlane(cnt);
 }
 
+// The complex128 form (rot_loop_f64m4.inc): 40-byte records, the lane sign
+// applied as a factor of +-1.0; same contract.
 #include "rot_loop_f64m4.inc"
 __device__ __forceinline__ void rot_loop(Cx<double> (&amp)[16], uint32_t k0, uint64_t tb,
                                          uint32_t &plo, uint32_t &phi, uint32_t &cnt) {
@@ -365,12 +363,16 @@ __device__ __forceinline__ void rot_loop(Cx<double> (&amp)[16], uint32_t k0, uin
     cnt = __builtin_amdgcn_readfirstlane(cnt);
 }
 
+// Applies rotations [0, count) of `rots` to the thread's coset.
+// k0: coset representative in the frame of rec.z (32-bit in a tile frame);
+// tbase: the tile index whose parity with rec.zhigh adds to the sign (0 for
+// span passes).
 template <typename T, int M, typename K0>
 __device__ __forceinline__ void apply_rots(Cx<T> (&amp)[1 << M], K0 k0, uint64_t tbase,
                                            const RotRec<T> *__restrict__ rots, uint32_t count) {
     if constexpr (M == 4 && sizeof(K0) == 4) {
-        // tile chunks at complex64: the threaded loop, stopping for the
-        // diagonal records, which take the compiled path below
+        // rank-4 tile chunks: the threaded loop, stopping for the diagonal
+        // records, which take the compiled path below
         const uint64_t p0 = (uint64_t)rots;
         uint32_t plo = __builtin_amdgcn_readfirstlane((uint32_t)p0);
         uint32_t phi = __builtin_amdgcn_readfirstlane((uint32_t)(p0 >> 32));
