@@ -353,3 +353,31 @@ def test_relabel_is_ignored_on_small_states_and_uniform_usage():
     assert P.prx_plan_get_info(pl)["relabel_passes"] == 0
     P.prx_plan_destroy(pl)
     P.prx_sched_destroy(s)
+
+
+@pytest.mark.parametrize("dtype,B", [(P.PRX_C64, 12), (P.PRX_C64, 14), (P.PRX_C128, 12),
+                                     (P.PRX_C128, 13)])
+def test_tile_passes_keep_at_least_16_contiguous_amplitudes(dtype, B):
+    """Whatever virtual-qubit count is asked for, every tile pass keeps b >= 4
+    low index bits (16 contiguous amplitudes per tile): the tile kernels'
+    16-byte groups and chunk layouts are built for that, and a planner that
+    went below it would hand the kernel a frame it was not written for."""
+    n = 20
+    x, z, h = synth.jw_hamiltonian(n, 300, 3)
+    H = P.prx_ham_create(n, x, z, h)
+    s = P.prx_sched_trotter(H, 1, 1.0, 1, P.PRX_REORDER_SUFFIX)
+    _, rx, _, _ = P.prx_sched_view(s)
+    seen = 0
+    for mv in (10, 8, 5):
+        for extra in ({}, dict(tile_only=1), dict(commuting=1)):
+            opts = dict(tile_qubits=B, chunk_rank=4, max_virtual=mv, **extra)
+            pl = P.prx_plan_create(s, n, dtype, 0, len(rx), P.PRX_FUSED, opts)
+            for i in range(P.prx_plan_get_info(pl)["passes"]):
+                ps = P.prx_plan_pass(pl, i)
+                if ps["kind"] == 2:
+                    assert ps["b"] >= 4 and ps["b"] + ps["g"] == B, (opts, ps["b"], ps["g"])
+                    seen += 1
+            P.prx_plan_destroy(pl)
+    assert seen > 0
+    P.prx_sched_destroy(s)
+    P.prx_ham_destroy(H)
